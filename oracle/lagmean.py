@@ -77,7 +77,10 @@ def irfft2(a: np.ndarray, N: int) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 def _f_h(u, v, h, z, p):
-    return h
+    # the depth is averaged as its anomaly h - H; H is added to the outputs
+    # (the average is linear in f and exact for constants, eq. (2.4)), which
+    # keeps the accumulators free of the large constant part
+    return h - p.H
 
 
 def _f_zeta(u, v, h, z, p):
@@ -103,6 +106,11 @@ def _f_one(u, v, h, z, p):
 BUILTIN_FIELDS: Dict[str, Callable] = {
     "h": _f_h, "zeta": _f_zeta, "q": _f_q, "u": _f_u, "v": _f_v, "one": _f_one,
 }
+
+
+def field_offset(name: str, p) -> float:
+    """Constant removed from an averaged field before accumulation."""
+    return p.H if name == "h" else 0.0
 
 
 @dataclass
@@ -185,7 +193,8 @@ class Run:
 
     State entries (spectral, rfft2 layout): 'u','v','h' (dynamic mode only),
     'xi_x','xi_y','gbar:<f>' (strategy 2), 'gtil:<f>','P_x','P_y' (strategy 1),
-    'E:<f>' (Eulerian accumulator), for every averaged field name <f>.
+    'E:<f>' (Eulerian accumulator), for every averaged field name <f>.  The
+    accumulators of 'h' integrate the anomaly h - H (see ``field_offset``).
     """
 
     def __init__(self, p: Params, u0=None, v0=None, h0=None):
@@ -333,9 +342,10 @@ class Run:
             "S1_eta_y": irfft2(self.Y["P_y"], N) / T,
         }
         for m in self.fields:
-            out[f"S2_mean:{m}"] = irfft2(self.Y[f"gbar:{m}"], N) / T
-            out[f"S1_mean:{m}"] = irfft2(self.Y[f"gtil:{m}"], N) / T
-            out[f"E_mean:{m}"] = irfft2(self.Y[f"E:{m}"], N) / T
+            c = field_offset(m, self.p)
+            out[f"S2_mean:{m}"] = irfft2(self.Y[f"gbar:{m}"], N) / T + c
+            out[f"S1_mean:{m}"] = irfft2(self.Y[f"gtil:{m}"], N) / T + c
+            out[f"E_mean:{m}"] = irfft2(self.Y[f"E:{m}"], N) / T + c
         self.T = T
         self.outputs = out
         return out
