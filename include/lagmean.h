@@ -1,0 +1,178 @@
+/*
+ * lagmean.h - C ABI of the MI355X (gfx950) Lagrangian-mean library.
+ *
+ * The library advances the doubly periodic rotating shallow-water equations
+ * pseudospectrally and, in the same classical RK4 stages, integrates the
+ * Lagrangian-mean PDEs of Kafiabad & Vanneste, "Computing Lagrangian means":
+ *
+ *   strategy 1 (section 3.1; numerics section 4.1): the partial mean f~ in the
+ *     form g~ = (t - tau) f~, eq. (4.1) (from eq. (3.5)), and the inverse lift
+ *     map Xi^{-1} of eq. (3.9), carried as P = (t - tau)(x - Xi^{-1});
+ *   strategy 2 (section 3.2; numerics section 4.2): the displacement
+ *     xi = Xi - x and g-bar = (t - tau) f-bar, eqs. (4.5a,b), with periodic
+ *     bilinear interpolation of u and f at x + xi;
+ *   the Eulerian mean, for comparison;
+ *
+ * over successive averaging intervals (tau, tau + T) (section 3, the
+ * paragraph after eq. (3.3): each interval is independent).  The averaged
+ * fields are the total depth h and the vorticity zeta = dv/dx - du/dy.
+ *
+ * Dynamics (section 4.2, eq. (4.6), in dimensional vector-invariant form):
+ *   du/dt = zeta v + f v - d(K + g h)/dx - nu8 |k|^8 u,
+ *   dv/dt = -zeta u - f u - d(K + g h)/dy - nu8 |k|^8 v,
+ *   dh/dt = -div(h u) - nu8 |k|^8 h,         K = (u^2 + v^2)/2,
+ * on [0, 2 pi)^2 with the 2/3-rule square mask |kx|, |ky| <= floor((N-1)/3)
+ * applied to the state and to every right-hand side (sections 4.1, 4.2.1).
+ * At t = tau, where xi/(t - tau) is 0/0, the partial-mean velocity takes its
+ * limit u/2.
+ *
+ * Conventions shared by every entry point:
+ *   - Physical arrays are N x N float64, row-major [iy][ix], x_i = 2 pi i / N,
+ *     for both precisions.
+ *   - Pointers flagged on_device = 1 are HIP device pointers, otherwise host
+ *     pointers.  The caller owns them; the library copies and never retains them.
+ *   - Every call returns an lm_status; nothing throws across the ABI.  After an
+ *     error, lm_last_error() (thread-local) describes it and the run is left as
+ *     it was before the call, except for LM_E_HIP (device state is then undefined).
+ *   - A run is driven by one thread at a time; distinct runs may be driven
+ *     from different threads.  All device work of a run is ordered on the HIP
+ *     stream given to lm_create (0 = the null stream).
+ */
+#ifndef LAGMEAN_H
+#define LAGMEAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LM_OK = 0,
+  LM_E_ARG = -1,         /* bad argument (null pointer, out-of-range value) */
+  LM_E_STATE = -2,       /* call out of order (e.g. end_interval with no steps) */
+  LM_E_OOM = -3,         /* device allocation failed */
+  LM_E_HIP = -4,         /* a HIP runtime call failed */
+  LM_E_NONFINITE = -5,   /* a NaN or Inf reached the interval outputs */
+  LM_E_UNSUPPORTED = -6, /* configuration not implemented (N, mode, ...) */
+  LM_E_BUDGET = -7       /* footprint exceeds a caller-given budget */
+} lm_status;
+
+typedef enum { LM_FP64 = 0, LM_FP32_MIXED = 1 } lm_precision;
+
+/* averaged fields (bit mask); the library averages h and zeta */
+#define LM_F_H 1u
+#define LM_F_ZETA 2u
+/* strategies (bit mask); the library always integrates all three */
+#define LM_S1 1u
+#define LM_S2 2u
+#define LM_EULER 4u
+/* gather interpolation */
+#define LM_INTERP_BILINEAR 0
+/* driver of u, v, h */
+#define LM_DYNAMIC 0
+
+typedef struct {
+  int32_t n;           /* grid points per side: 64, 128, 256, 512 or 1024 */
+  int32_t precision;   /* LM_FP64: everything float64.  LM_FP32_MIXED: transforms,
+                          products and gathers in float32; the xi and P state, their
+                          RK4 accumulators and the end-of-interval outputs (division
+                          by T included) in float64 */
+  double f, g, H;      /* Coriolis parameter, gravity, mean depth */
+  double dt;           /* time step (shared by dynamics and mean PDEs) */
+  double nu8;          /* eighth-order hyperviscosity on u, v, h (>= 0) */
+  uint32_t avg_fields; /* must be LM_F_H | LM_F_ZETA (or 0 for the default) */
+  uint32_t strategies; /* must be LM_S1 | LM_S2 | LM_EULER (or 0 for the default) */
+  int32_t interp;      /* LM_INTERP_BILINEAR */
+  int32_t mode;        /* LM_DYNAMIC */
+} lm_config;
+
+typedef struct lm_run lm_run;
+
+/* Device bytes lm_create would allocate for this configuration.  Host only,
+   allocates nothing.  LM_E_UNSUPPORTED / LM_E_ARG as lm_create. */
+lm_status lm_query_footprint(const lm_config* cfg, size_t* bytes);
+
+/* Create a run: validates cfg, allocates all device buffers of the run (one
+   allocation), builds twiddle tables.  hip_stream: a hipStream_t (may be 0).
+   The state is undefined until lm_set_state.  *out receives the handle. */
+lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out);
+
+/* Set the dynamical state from physical u, v, h (h = total depth), each N x N
+   float64.  The fields are transformed and truncated to the 2/3-rule mask.
+   Resets the step counter to 0; the averaging state is cleared and no interval
+   is open.  Synchronous with respect to the caller's buffers. */
+lm_status lm_set_state(lm_run* run, const double* u, const double* v, const double* h, int on_device);
+
+/* Physical u, v, h of the current (masked) state, N x N float64 each.  Synchronous. */
+lm_status lm_get_state(lm_run* run, double* u, double* v, double* h, int on_device);
+
+/* Open an averaging interval at the current time: tau := t, and zero the
+   strategy-1, strategy-2 and Eulerian state (their initial conditions: section
+   3.2 and eq. (4.1): g = 0, xi = 0, P = 0).  LM_E_STATE before lm_set_state. */
+lm_status lm_begin_interval(lm_run* run);
+
+/* Advance nsteps >= 0 RK4 steps.  Asynchronous on the run's stream.
+   LM_E_STATE before lm_set_state. */
+lm_status lm_step(lm_run* run, int32_t nsteps);
+
+/* As lm_step, but every kernel launch is bracketed by HIP events on the run's
+   stream and the stream is synchronised after each RK4 stage.  ms_avg[0..2]
+   receive the average duration in milliseconds of the three hot-path kernels:
+   [0] rows pass of the dynamics, [1] rows pass of the mean right-hand sides,
+   [2] column pass (spectral assembly + RK4).  nsteps > 0.  For measurement. */
+lm_status lm_step_profiled(lm_run* run, int32_t nsteps, double* ms_avg);
+
+/* Close the interval: T = (steps since begin) * dt; computes the outputs
+   (section 4.1: f~^L = g~/T, eta = P/T; section 4.2: f-bar^L = g-bar/T and xi;
+   Eulerian mean E/T) in float64 and synchronises the stream.  LM_E_STATE if no
+   interval is open or it holds no step; LM_E_NONFINITE if any output is NaN or
+   Inf (outputs are still readable).  *T_out (may be null) receives T. */
+lm_status lm_end_interval(lm_run* run, double* T_out);
+
+/* output kinds for lm_read_mean */
+typedef enum {
+  LM_K_S2_MEAN = 0,   /* strategy 2: f-bar^L at Lagrangian-mean positions (field) */
+  LM_K_S2_XI_X = 1,   /* strategy 2: xi_x = Xi_x(x, tau+T) - x               */
+  LM_K_S2_XI_Y = 2,   /* strategy 2: xi_y                                   */
+  LM_K_S1_MEAN = 3,   /* strategy 1: f~^L at end-of-interval positions (field) */
+  LM_K_S1_ETA_X = 4,  /* strategy 1: eta_x = x - Xi^{-1}_x(x, tau+T)          */
+  LM_K_S1_ETA_Y = 5,  /* strategy 1: eta_y                                  */
+  LM_K_EULER_MEAN = 6 /* Eulerian time mean (field)                         */
+} lm_kind;
+typedef enum { LM_FIELD_H = 0, LM_FIELD_ZETA = 1 } lm_field;
+
+/* Copy one output of the last closed interval (N x N float64) to out.
+   field is ignored for the displacement kinds.  LM_E_STATE before the first
+   lm_end_interval.  Synchronous. */
+lm_status lm_read_mean(lm_run* run, int32_t field, int32_t kind, double* out, int on_device);
+
+/* raw prognostic fields for lm_peek */
+typedef enum {
+  LM_P_U = 0, LM_P_V, LM_P_H, LM_P_GBAR_H, LM_P_GBAR_ZETA, LM_P_GTIL_H, LM_P_GTIL_ZETA,
+  LM_P_E_H, LM_P_E_ZETA, LM_P_XI_X, LM_P_XI_Y, LM_P_P_X, LM_P_P_Y
+} lm_peek_field;
+
+/* Physical value of one raw prognostic field of the current state (e.g.
+   g-bar = (t - tau) f-bar undivided), N x N float64.  The accumulators of h
+   (LM_P_GBAR_H, LM_P_GTIL_H, LM_P_E_H) integrate the anomaly h - H.
+   Synchronous.  For tests. */
+lm_status lm_peek(lm_run* run, int32_t which, double* out, int on_device);
+
+/* Steps taken since lm_set_state and since lm_begin_interval. */
+lm_status lm_counters(lm_run* run, int64_t* steps, int64_t* steps_in_interval);
+
+/* Release every device buffer of the run (waits for its stream).  Null is a no-op. */
+lm_status lm_destroy(lm_run* run);
+
+/* Text of a status code (static storage). */
+const char* lm_status_str(lm_status s);
+/* Last error message of the calling thread ("" if none). */
+const char* lm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAGMEAN_H */

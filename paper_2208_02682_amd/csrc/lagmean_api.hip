@@ -1,0 +1,382 @@
+// C ABI of the Lagrangian-mean library: argument checking, run management and
+// the order of launches.  The kernels are launched through the per-N launchers
+// (launch.hpp); hot-path kernels are in step_kernels.hpp, boundary transforms in
+// io_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "lagmean.h"
+#include "launch.hpp"
+
+using lm::cplx;
+
+namespace {
+
+thread_local std::string g_err;
+
+lm_status fail(lm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(LM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool supported_n(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+
+lm_status check_cfg(const lm_config* cfg) {
+  if (!cfg) return fail(LM_E_ARG, "null config");
+  if (!supported_n(cfg->n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 256, 512 or 1024");
+  if (cfg->precision != LM_FP64 && cfg->precision != LM_FP32_MIXED)
+    return fail(LM_E_ARG, "precision must be LM_FP64 or LM_FP32_MIXED");
+  if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return fail(LM_E_ARG, "dt must be positive and finite");
+  if (!(cfg->nu8 >= 0.0) || !std::isfinite(cfg->nu8)) return fail(LM_E_ARG, "nu8 must be >= 0");
+  if (!std::isfinite(cfg->f) || !std::isfinite(cfg->g) || !std::isfinite(cfg->H))
+    return fail(LM_E_ARG, "f, g, H must be finite");
+  if (cfg->avg_fields != 0 && cfg->avg_fields != (LM_F_H | LM_F_ZETA))
+    return fail(LM_E_UNSUPPORTED, "averaged fields are h and zeta");
+  if (cfg->strategies != 0 && cfg->strategies != (LM_S1 | LM_S2 | LM_EULER))
+    return fail(LM_E_UNSUPPORTED, "all of strategy 1, strategy 2 and the Eulerian mean are integrated");
+  if (cfg->interp != LM_INTERP_BILINEAR) return fail(LM_E_UNSUPPORTED, "bilinear interpolation only");
+  if (cfg->mode != LM_DYNAMIC) return fail(LM_E_UNSUPPORTED, "dynamic mode only");
+  return LM_OK;
+}
+
+}  // namespace
+
+struct lm_run : lm::RunView {
+  lm_config cfg;
+  bool has_state, in_interval, has_mean;
+  double T;
+};
+
+namespace {
+
+// state field -> (pointer, is_float32)
+std::pair<const void*, int> state_field(lm_run* r, int which) {
+  const size_t sp = r->d.spec_elems();
+  const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  static const int rmap[9] = {lm::SF_U, lm::SF_V, lm::SF_H, lm::SF_GBH, lm::SF_GBZ,
+                              lm::SF_GTH, lm::SF_GTZ, lm::SF_EH, lm::SF_EZ};
+  if (which >= LM_P_U && which <= LM_P_E_ZETA)
+    return {r->slab + r->L.Yr + rmap[which] * sp * cT, r->fp32 ? 1 : 0};
+  static const int dmap[4] = {lm::SD_XIX, lm::SD_XIY, lm::SD_PX, lm::SD_PY};
+  return {r->slab + r->L.Yd + dmap[which - LM_P_XI_X] * sp * sizeof(cplx<double>), 0};
+}
+
+lm_status copy_in(lm_run* r, double* dst, const double* src, int on_device) {
+  const size_t bytes = (size_t)r->d.N * r->d.N * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, r->stream));
+  return LM_OK;
+}
+lm_status copy_out(lm_run* r, double* dst, const double* src, int on_device) {
+  const size_t bytes = (size_t)r->d.N * r->d.N * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, r->stream));
+  return LM_OK;
+}
+
+lm_status zero_means(lm_run* r) {
+  const size_t sp = r->d.spec_elems();
+  const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  HIP_TRY(hipMemsetAsync(r->slab + r->L.Yr + lm::SF_GBH * sp * cT, 0, (lm::NSF_R - lm::SF_GBH) * sp * cT, r->stream));
+  HIP_TRY(hipMemsetAsync(r->slab + r->L.Yd, 0, lm::NSF_D * sp * sizeof(cplx<double>), r->stream));
+  return LM_OK;
+}
+
+lm_status check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return LM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lm_status_str(lm_status s) {
+  switch (s) {
+    case LM_OK: return "ok";
+    case LM_E_ARG: return "invalid argument";
+    case LM_E_STATE: return "call out of order";
+    case LM_E_OOM: return "out of device memory";
+    case LM_E_HIP: return "HIP runtime error";
+    case LM_E_NONFINITE: return "non-finite values in the outputs";
+    case LM_E_UNSUPPORTED: return "unsupported configuration";
+    case LM_E_BUDGET: return "footprint exceeds the budget";
+  }
+  return "unknown status";
+}
+
+const char* lm_last_error(void) { return g_err.c_str(); }
+
+lm_status lm_query_footprint(const lm_config* cfg, size_t* bytes) {
+  lm_status s = check_cfg(cfg);
+  if (s != LM_OK) return s;
+  if (!bytes) return fail(LM_E_ARG, "null bytes");
+  *bytes = lm::make_layout(lm::Dims::make(cfg->n), cfg->precision == LM_FP32_MIXED).total;
+  return LM_OK;
+}
+
+lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
+  lm_status s = check_cfg(cfg);
+  if (s != LM_OK) return s;
+  if (!out) return fail(LM_E_ARG, "null out");
+  *out = nullptr;
+  lm_run* r = new lm_run();
+  r->cfg = *cfg;
+  r->d = lm::Dims::make(cfg->n);
+  r->ph = lm::Phys{cfg->f, cfg->g, cfg->H, cfg->dt, cfg->nu8};
+  r->stream = (hipStream_t)hip_stream;
+  r->fp32 = cfg->precision == LM_FP32_MIXED;
+  r->L = lm::make_layout(r->d, r->fp32);
+  r->n = r->n_tau = 0;
+  r->has_state = r->in_interval = r->has_mean = false;
+  r->T = 0.0;
+  r->ys_cur = 0;
+  r->slab = nullptr;
+  hipError_t e = hipMalloc((void**)&r->slab, r->L.total);
+  if (e != hipSuccess) {
+    delete r;
+    (void)hipGetLastError();
+    return fail(LM_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  // twiddles exp(-2 pi i m / N), long double on the host
+  const int N = r->d.N;
+  std::vector<cplx<double>> tw(N);
+  std::vector<cplx<float>> twf(N);
+  for (int m = 0; m < N; ++m) {
+    const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)N;
+    tw[m] = {(double)cosl(a), (double)sinl(a)};
+    twf[m] = {(float)cosl(a), (float)sinl(a)};
+  }
+  e = hipMemcpy(r->slab + r->L.tw64, tw.data(), N * sizeof(cplx<double>), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = r->fp32 ? hipMemcpy(r->slab + r->L.twT, twf.data(), N * sizeof(cplx<float>), hipMemcpyHostToDevice)
+                : hipMemcpy(r->slab + r->L.twT, tw.data(), N * sizeof(cplx<double>), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(r->slab, 0, r->L.tw64);
+  if (e != hipSuccess) {
+    (void)hipFree(r->slab);
+    delete r;
+    return fail(LM_E_HIP, std::string("init: ") + hipGetErrorString(e));
+  }
+  *out = r;
+  return LM_OK;
+}
+
+lm_status lm_set_state(lm_run* r, const double* u, const double* v, const double* h, int on_device) {
+  if (!r || !u || !v || !h) return fail(LM_E_ARG, "null argument");
+  const size_t nn = (size_t)r->d.N * r->d.N;
+  double* phys = (double*)r->at(r->L.phys);
+  lm_status s;
+  if ((s = copy_in(r, phys, u, on_device)) != LM_OK) return s;
+  if ((s = copy_in(r, phys + nn, v, on_device)) != LM_OK) return s;
+  if ((s = copy_in(r, phys + 2 * nn, h, on_device)) != LM_OK) return s;
+  const size_t rf = r->d.rowfield_elems();
+  cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
+  lm::IoRowFwd J{};
+  J.a[0] = phys; J.b[0] = phys + nn; J.oa[0] = ioC; J.ob[0] = ioC + rf;
+  J.a[1] = phys + 2 * nn; J.b[1] = nullptr; J.oa[1] = ioC + 2 * rf; J.ob[1] = nullptr;
+  LM_DISPATCH_N(r->d.N, lm::launch_io_row_forward, *r, J, 2);
+  lm::IoColFwd K{};
+  const size_t sp = r->d.spec_elems();
+  const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  for (int q = 0; q < 3; ++q) {
+    K.src[q] = ioC + q * rf;
+    K.dst[q] = r->slab + r->L.Yr + q * sp * cT;  // SF_U, SF_V, SF_H are 0, 1, 2
+    K.dst_f32[q] = r->fp32 ? 1 : 0;
+  }
+  LM_DISPATCH_N(r->d.N, lm::launch_io_col_forward, *r, K, 3);
+  if ((s = zero_means(r)) != LM_OK) return s;
+  r->ys_cur = 0;
+  LM_DISPATCH_N(r->d.N, lm::launch_prologue, *r);
+  if ((s = check_launch()) != LM_OK) return s;
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  r->n = r->n_tau = 0;
+  r->has_state = true;
+  r->in_interval = false;
+  return LM_OK;
+}
+
+lm_status lm_get_state(lm_run* r, double* u, double* v, double* h, int on_device) {
+  if (!r || !u || !v || !h) return fail(LM_E_ARG, "null argument");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  const size_t nn = (size_t)r->d.N * r->d.N, rf = r->d.rowfield_elems();
+  cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
+  double* phys = (double*)r->at(r->L.phys);
+  lm::IoColInv J{};
+  for (int q = 0; q < 3; ++q) {
+    auto f = state_field(r, LM_P_U + q);
+    J.src[q] = f.first;
+    J.src_f32[q] = f.second;
+    J.dst[q] = ioC + q * rf;
+  }
+  LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, J, 3);
+  lm::IoRowInv K{};
+  K.a[0] = ioC; K.b[0] = ioC + rf; K.oa[0] = phys; K.ob[0] = phys + nn; K.sa[0] = K.sb[0] = 1.0;
+  K.a[1] = ioC + 2 * rf; K.b[1] = nullptr; K.oa[1] = phys + 2 * nn; K.ob[1] = nullptr; K.sa[1] = 1.0;
+  LM_DISPATCH_N(r->d.N, lm::launch_io_row_inverse, *r, K, 2);
+  lm_status s;
+  if ((s = check_launch()) != LM_OK) return s;
+  if ((s = copy_out(r, u, phys, on_device)) != LM_OK) return s;
+  if ((s = copy_out(r, v, phys + nn, on_device)) != LM_OK) return s;
+  if ((s = copy_out(r, h, phys + 2 * nn, on_device)) != LM_OK) return s;
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  return LM_OK;
+}
+
+lm_status lm_begin_interval(lm_run* r) {
+  if (!r) return fail(LM_E_ARG, "null run");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  lm_status s;
+  if ((s = zero_means(r)) != LM_OK) return s;
+  LM_DISPATCH_N(r->d.N, lm::launch_prologue, *r);
+  if ((s = check_launch()) != LM_OK) return s;
+  r->n_tau = r->n;
+  r->in_interval = true;
+  return LM_OK;
+}
+
+lm_status lm_step(lm_run* r, int32_t nsteps) {
+  if (!r) return fail(LM_E_ARG, "null run");
+  if (nsteps < 0) return fail(LM_E_ARG, "nsteps < 0");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  LM_DISPATCH_N(r->d.N, lm::launch_steps, *r, nsteps);
+  return check_launch();
+}
+
+lm_status lm_step_profiled(lm_run* r, int32_t nsteps, double* ms_avg) {
+  if (!r || !ms_avg) return fail(LM_E_ARG, "null argument");
+  if (nsteps <= 0) return fail(LM_E_ARG, "nsteps must be positive");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  double ms[3] = {0.0, 0.0, 0.0};
+  hipError_t e = hipSuccess;
+  LM_DISPATCH_N_RET(r->d.N, e, lm::launch_steps_profiled, *r, nsteps, ms);
+  if (e != hipSuccess) return fail(LM_E_HIP, std::string("profiled step: ") + hipGetErrorString(e));
+  lm_status s = check_launch();
+  if (s != LM_OK) return s;
+  for (int i = 0; i < 3; ++i) ms_avg[i] = ms[i] / (4.0 * nsteps);
+  return LM_OK;
+}
+
+lm_status lm_end_interval(lm_run* r, double* T_out) {
+  if (!r) return fail(LM_E_ARG, "null run");
+  if (!r->in_interval) return fail(LM_E_STATE, "no open interval");
+  if (r->n == r->n_tau) return fail(LM_E_STATE, "interval holds no step");
+  const double T = double(r->n - r->n_tau) * r->ph.dt;
+  const size_t nn = (size_t)r->d.N * r->d.N, rf = r->d.rowfield_elems();
+  cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
+  double* out = (double*)r->at(r->L.out);
+  // accumulators in output order: (gbar_h, gbar_z), (xi_x, xi_y), (gtil_h, gtil_z), (P_x, P_y), (E_h, E_z)
+  static const int order[10] = {LM_P_GBAR_H, LM_P_GBAR_ZETA, LM_P_XI_X, LM_P_XI_Y, LM_P_GTIL_H,
+                                LM_P_GTIL_ZETA, LM_P_P_X, LM_P_P_Y, LM_P_E_H, LM_P_E_ZETA};
+  for (int half = 0; half < 2; ++half) {
+    lm::IoColInv J{};
+    for (int q = 0; q < 5; ++q) {
+      auto f = state_field(r, order[half * 5 + q]);
+      J.src[q] = f.first;
+      J.src_f32[q] = f.second;
+      J.dst[q] = ioC + (half * 5 + q) * rf;
+    }
+    LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, J, 5);
+  }
+  lm::IoRowInv K{};
+  for (int p = 0; p < 5; ++p) {
+    K.a[p] = ioC + (2 * p) * rf;
+    K.b[p] = ioC + (2 * p + 1) * rf;
+    K.oa[p] = out + (2 * p) * nn;
+    K.ob[p] = out + (2 * p + 1) * nn;
+    const double sc = (p == 1) ? 1.0 : 1.0 / T;  // xi is not divided
+    K.sa[p] = K.sb[p] = sc;
+    // the h accumulators integrate eta = h - H: the mean of h is H + (mean of eta)
+    K.ca[p] = (p == 0 || p == 2 || p == 4) ? r->ph.H : 0.0;
+    K.cb[p] = 0.0;
+  }
+  LM_DISPATCH_N(r->d.N, lm::launch_io_row_inverse, *r, K, 5);
+  int* flag = (int*)r->at(r->L.flag);
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), r->stream));
+  lm::launch_nonfinite(*r, out, 10 * nn, flag);
+  lm_status s;
+  if ((s = check_launch()) != LM_OK) return s;
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, r->stream));
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  r->T = T;
+  r->has_mean = true;
+  r->in_interval = false;
+  if (T_out) *T_out = T;
+  if (hflag) return fail(LM_E_NONFINITE, "non-finite values in the interval outputs");
+  return LM_OK;
+}
+
+lm_status lm_read_mean(lm_run* r, int32_t field, int32_t kind, double* out_, int on_device) {
+  if (!r || !out_) return fail(LM_E_ARG, "null argument");
+  if (!r->has_mean) return fail(LM_E_STATE, "no closed interval");
+  if (field != LM_FIELD_H && field != LM_FIELD_ZETA) return fail(LM_E_ARG, "field must be LM_FIELD_H or LM_FIELD_ZETA");
+  int idx;
+  switch (kind) {
+    case LM_K_S2_MEAN: idx = 0 + field; break;
+    case LM_K_S2_XI_X: idx = 2; break;
+    case LM_K_S2_XI_Y: idx = 3; break;
+    case LM_K_S1_MEAN: idx = 4 + field; break;
+    case LM_K_S1_ETA_X: idx = 6; break;
+    case LM_K_S1_ETA_Y: idx = 7; break;
+    case LM_K_EULER_MEAN: idx = 8 + field; break;
+    default: return fail(LM_E_ARG, "unknown kind");
+  }
+  const size_t nn = (size_t)r->d.N * r->d.N;
+  lm_status s = copy_out(r, out_, (double*)r->at(r->L.out) + idx * nn, on_device);
+  if (s != LM_OK) return s;
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  return LM_OK;
+}
+
+lm_status lm_peek(lm_run* r, int32_t which, double* out_, int on_device) {
+  if (!r || !out_) return fail(LM_E_ARG, "null argument");
+  if (which < LM_P_U || which > LM_P_P_Y) return fail(LM_E_ARG, "unknown field");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
+  double* phys = (double*)r->at(r->L.phys);
+  lm::IoColInv J{};
+  auto f = state_field(r, which);
+  J.src[0] = f.first;
+  J.src_f32[0] = f.second;
+  J.dst[0] = ioC;
+  LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, J, 1);
+  lm::IoRowInv K{};
+  K.a[0] = ioC; K.b[0] = nullptr; K.oa[0] = phys; K.ob[0] = nullptr; K.sa[0] = 1.0;
+  LM_DISPATCH_N(r->d.N, lm::launch_io_row_inverse, *r, K, 1);
+  lm_status s;
+  if ((s = check_launch()) != LM_OK) return s;
+  if ((s = copy_out(r, out_, phys, on_device)) != LM_OK) return s;
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  return LM_OK;
+}
+
+lm_status lm_counters(lm_run* r, int64_t* steps, int64_t* steps_in_interval) {
+  if (!r) return fail(LM_E_ARG, "null run");
+  if (steps) *steps = r->n;
+  if (steps_in_interval) *steps_in_interval = r->in_interval ? r->n - r->n_tau : 0;
+  return LM_OK;
+}
+
+lm_status lm_destroy(lm_run* r) {
+  if (!r) return LM_OK;
+  hipError_t e = hipStreamSynchronize(r->stream);
+  hipError_t e2 = hipFree(r->slab);
+  delete r;
+  if (e != hipSuccess) return fail(LM_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(LM_E_HIP, std::string("hipFree: ") + hipGetErrorString(e2));
+  return LM_OK;
+}
+
+}  // extern "C"

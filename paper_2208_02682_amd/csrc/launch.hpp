@@ -1,0 +1,39 @@
+// Per-N launchers (explicitly instantiated in inst_<N>.hip so that the
+// kernels of different grid sizes compile in parallel).
+#pragma once
+
+#include "io_structs.hpp"
+#include "run_view.hpp"
+
+namespace lm {
+
+template <int N> void launch_steps(RunView& r, int nsteps);   // nsteps RK4 steps
+template <int N> hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms);  // + kernel times
+template <int N> void launch_prologue(RunView& r);            // column pass of the current state
+template <int N> void launch_io_row_forward(RunView& r, const IoRowFwd& J, int count);
+template <int N> void launch_io_col_forward(RunView& r, const IoColFwd& J, int count);
+template <int N> void launch_io_col_inverse(RunView& r, const IoColInv& J, int count);
+template <int N> void launch_io_row_inverse(RunView& r, const IoRowInv& J, int count);
+void launch_nonfinite(RunView& r, const double* a, size_t n, int* flag);
+
+#define LM_DISPATCH_N_RET(n, out, FN, ...)       \
+  switch (n) {                                    \
+    case 64: out = FN<64>(__VA_ARGS__); break;    \
+    case 128: out = FN<128>(__VA_ARGS__); break;  \
+    case 256: out = FN<256>(__VA_ARGS__); break;  \
+    case 512: out = FN<512>(__VA_ARGS__); break;  \
+    case 1024: out = FN<1024>(__VA_ARGS__); break;\
+    default: break;                               \
+  }
+
+#define LM_DISPATCH_N(n, FN, ...)            \
+  switch (n) {                               \
+    case 64: FN<64>(__VA_ARGS__); break;     \
+    case 128: FN<128>(__VA_ARGS__); break;   \
+    case 256: FN<256>(__VA_ARGS__); break;   \
+    case 512: FN<512>(__VA_ARGS__); break;   \
+    case 1024: FN<1024>(__VA_ARGS__); break; \
+    default: break;                          \
+  }
+
+}  // namespace lm

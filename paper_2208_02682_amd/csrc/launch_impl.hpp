@@ -1,0 +1,159 @@
+// Definitions of the per-N launchers declared in launch.hpp.
+#pragma once
+
+#include <type_traits>
+
+#include "io_kernels.hpp"
+#include "launch.hpp"
+#include "step_kernels.hpp"
+
+namespace lm {
+
+template <typename T>
+StepPtrs<T> step_ptrs(RunView& r) {
+  StepPtrs<T> P;
+  P.Yr = (cplx<T>*)r.at(r.L.Yr);
+  P.Yd = (cplx<double>*)r.at(r.L.Yd);
+  P.Ar = (cplx<T>*)r.at(r.L.Ar);
+  P.Ad = (cplx<double>*)r.at(r.L.Ad);
+  P.IC = (cplx<T>*)r.at(r.L.IC);
+  P.RS = (cplx<T>*)r.at(r.L.RS);
+  P.uvhz = (P4<T>*)r.at(r.L.uvhz);
+  P.tw = (const cplx<T>*)r.at(std::is_same<T, double>::value ? r.L.tw64 : r.L.twT);
+  return P;
+}
+
+template <int N>
+dim3 row_grid(int tasks) {
+  constexpr int PW = 64 / (N / 16);
+  constexpr int rows = ROW_WAVES * PW;
+  return dim3((N + rows - 1) / rows, tasks);
+}
+template <int N>
+dim3 col_grid(const Dims& d, int groups) {
+  constexpr int C = col_tile(N);
+  return dim3((d.NKX + C - 1) / C, groups);
+}
+template <int N>
+dim3 col_block() {
+  return dim3(col_tile(N) * (N / 16));
+}
+
+template <typename T, int N>
+void launch_columns_t(RunView& r, int stage) {
+  const StepPtrs<T> P = step_ptrs<T>(r);
+  cplx<T>* Ys[2] = {(cplx<T>*)r.at(r.L.Ys0), (cplx<T>*)r.at(r.L.Ys1)};
+  const cplx<T>* Ys_in = Ys[r.ys_cur];
+  cplx<T>* Ys_out = (stage < 0) ? Ys[r.ys_cur] : Ys[r.ys_cur ^ 1];
+  hipLaunchKernelGGL((k_columns<T, N>), col_grid<N>(r.d, NCG), col_block<N>(), 0, r.stream, P, r.d, r.ph, stage,
+                     Ys_in, Ys_out);
+  if (stage >= 0) r.ys_cur ^= 1;
+}
+
+template <typename T, int N>
+void launch_steps_t(RunView& r, int nsteps) {
+  const StepPtrs<T> P = step_ptrs<T>(r);
+  static const double c[4] = {0.0, 0.5, 0.5, 1.0};
+  for (int s = 0; s < nsteps; ++s) {
+    for (int stage = 0; stage < 4; ++stage) {
+      // time since the interval start, from integers
+      const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d);
+      hipLaunchKernelGGL((k_rows_rhs<T, N>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
+      launch_columns_t<T, N>(r, stage);
+    }
+    r.n += 1;
+  }
+}
+
+// Same launches as launch_steps_t, each bracketed by events on the run's
+// stream; the stream is synchronised after every stage and the three kernel
+// durations are accumulated into ms[0..2].
+template <typename T, int N>
+hipError_t launch_steps_profiled_t(RunView& r, int nsteps, double* ms) {
+  const StepPtrs<T> P = step_ptrs<T>(r);
+  static const double c[4] = {0.0, 0.5, 0.5, 1.0};
+  hipEvent_t ev[6];
+  for (auto& e : ev) {
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+  }
+  hipError_t err = hipSuccess;
+  for (int s = 0; s < nsteps && err == hipSuccess; ++s) {
+    for (int stage = 0; stage < 4; ++stage) {
+      const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
+      (void)hipEventRecord(ev[0], r.stream);
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d);
+      (void)hipEventRecord(ev[1], r.stream);
+      hipLaunchKernelGGL((k_rows_rhs<T, N>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
+      (void)hipEventRecord(ev[2], r.stream);
+      (void)hipEventRecord(ev[3], r.stream);
+      launch_columns_t<T, N>(r, stage);
+      (void)hipEventRecord(ev[4], r.stream);
+      err = hipEventSynchronize(ev[4]);
+      if (err != hipSuccess) break;
+      float a = 0.f, b = 0.f, cc = 0.f;
+      (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+      (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+      (void)hipEventElapsedTime(&cc, ev[3], ev[4]);
+      ms[0] += a;
+      ms[1] += b;
+      ms[2] += cc;
+    }
+    r.n += 1;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return err;
+}
+
+template <int N>
+hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms) {
+  if (r.fp32) return launch_steps_profiled_t<float, N>(r, nsteps, ms);
+  return launch_steps_profiled_t<double, N>(r, nsteps, ms);
+}
+
+template <int N>
+void launch_steps(RunView& r, int nsteps) {
+  if (r.fp32) launch_steps_t<float, N>(r, nsteps);
+  else launch_steps_t<double, N>(r, nsteps);
+}
+
+template <int N>
+void launch_prologue(RunView& r) {
+  if (r.fp32) launch_columns_t<float, N>(r, -1);
+  else launch_columns_t<double, N>(r, -1);
+}
+
+template <int N>
+void launch_io_col_inverse(RunView& r, const IoColInv& J, int count) {
+  hipLaunchKernelGGL((k_io_col_inverse<N>), col_grid<N>(r.d, count), col_block<N>(), 0, r.stream, J, r.d,
+                     (const cplx<double>*)r.at(r.L.tw64));
+}
+template <int N>
+void launch_io_row_inverse(RunView& r, const IoRowInv& J, int count) {
+  hipLaunchKernelGGL((k_io_row_inverse<N>), row_grid<N>(count), dim3(64 * ROW_WAVES), 0, r.stream, J, r.d,
+                     (const cplx<double>*)r.at(r.L.tw64));
+}
+template <int N>
+void launch_io_row_forward(RunView& r, const IoRowFwd& J, int count) {
+  hipLaunchKernelGGL((k_io_row_forward<N>), row_grid<N>(count), dim3(64 * ROW_WAVES), 0, r.stream, J, r.d,
+                     (const cplx<double>*)r.at(r.L.tw64));
+}
+template <int N>
+void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
+  hipLaunchKernelGGL((k_io_col_forward<N>), col_grid<N>(r.d, count), col_block<N>(), 0, r.stream, J, r.d,
+                     (const cplx<double>*)r.at(r.L.tw64));
+}
+
+}  // namespace lm
+
+#define LM_INSTANTIATE(N)                                                                \
+  namespace lm {                                                                         \
+  template void launch_steps<N>(RunView&, int);                                          \
+  template hipError_t launch_steps_profiled<N>(RunView&, int, double*);                  \
+  template void launch_prologue<N>(RunView&);                                            \
+  template void launch_io_row_forward<N>(RunView&, const IoRowFwd&, int);                \
+  template void launch_io_col_forward<N>(RunView&, const IoColFwd&, int);                \
+  template void launch_io_col_inverse<N>(RunView&, const IoColInv&, int);                \
+  template void launch_io_row_inverse<N>(RunView&, const IoRowInv&, int);                \
+  }

@@ -1,0 +1,80 @@
+// Device data layout of one run (one doubly periodic N x N problem).
+//
+// Spectral state: only the 2/3-rule square |kx|, |ky| <= K, K = floor((N-1)/3),
+// is ever non-zero, so each field stores NKX = K+1 columns (kx = 0..K) of
+// NKY = 2K+1 entries (ky = -K..K, index ky + K), column-contiguous, complex.
+// Coefficients are normalised by 1/N^2 (physical value = plain inverse sum).
+//
+// Column-pass outputs ("intermediates") and row-pass outputs ("row spectra")
+// are [field][y][kx] with y = 0..N-1 and kx = 0..K (row stride NKXP >= NKX,
+// padded to 16 complex so row segments are 128-byte aligned).
+//
+// Physical dynamics fields u, v, h, zeta are stored interleaved per grid point
+// (one 4-vector) so that a bilinear gather corner is a single load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lm {
+
+// prognostic fields, in the order of the per-precision state arrays
+enum StateField : int {
+  // working precision; the h accumulators (GBH, GTH, EH) integrate eta = h - H
+  SF_U = 0, SF_V, SF_H, SF_GBH, SF_GBZ, SF_GTH, SF_GTZ, SF_EH, SF_EZ,
+  NSF_R = 9
+};
+enum StateFieldD : int {
+  SD_XIX = 0, SD_XIY, SD_PX, SD_PY,  // always float64 (displacement / position accumulators)
+  NSF_D = 4
+};
+
+// intermediates: inverse column transforms of the stage state
+enum Inter : int {
+  IC_U = 0, IC_V, IC_H, IC_UY,                  // u, v, eta = h - H and (i ky u)
+  IC_XIX, IC_XIX_Y, IC_XIY, IC_XIY_Y,           // xi components and their (i ky) versions
+  IC_GBH, IC_GBH_Y, IC_GBZ, IC_GBZ_Y,           // strategy-2 g
+  IC_GTH, IC_GTH_Y, IC_GTZ, IC_GTZ_Y,           // strategy-1 g
+  IC_PX, IC_PX_Y, IC_PY, IC_PY_Y,               // strategy-1 position accumulator P
+  NIC = 20
+};
+
+// row spectra: forward row transforms of the physical right-hand-side terms
+enum RowSpec : int {
+  RS_ZV = 0, RS_ZU, RS_K, RS_HU, RS_HV,         // zeta v, zeta u, (u^2+v^2)/2, eta u, eta v
+  RS_XIX, RS_XIY, RS_GBH, RS_GBZ, RS_GTH, RS_GTZ, RS_PX, RS_PY,
+  NRS = 13
+};
+
+// column-kernel work groups (one prognostic field each; E_h, E_zeta ride with h)
+enum ColGroup : int {
+  CG_U = 0, CG_V, CG_H, CG_XIX, CG_XIY, CG_GBH, CG_GBZ, CG_GTH, CG_GTZ, CG_PX, CG_PY,
+  NCG = 11
+};
+
+// row-kernel tasks of the right-hand-side pass
+enum RowTask : int { RT_XI = 0, RT_GBAR, RT_GTIL, RT_P, NRT = 4 };
+
+struct Dims {
+  int N, K, NKX, NKY, NKXP;
+  __host__ __device__ static Dims make(int N) {
+    Dims d;
+    d.N = N;
+    d.K = (N - 1) / 3;
+    d.NKX = d.K + 1;
+    d.NKY = 2 * d.K + 1;
+    d.NKXP = (d.NKX + 15) / 16 * 16;
+    return d;
+  }
+  __host__ __device__ size_t spec_elems() const { return (size_t)NKX * NKY; }
+  __host__ __device__ size_t rowfield_elems() const { return (size_t)N * NKXP; }
+};
+
+// physics constants of one run
+struct Phys {
+  double f, g, H, dt, nu8;
+};
+
+}  // namespace lm

@@ -1,0 +1,570 @@
+// Hot-path kernels of one RK4 stage (templated on the transform precision T and N).
+//
+// One stage of the coupled system is three launches:
+//
+//  rows_dyn   per grid row: inverse row transforms of the column-pass outputs to
+//             physical u, v, eta = h - H, zeta (zeta = dv/dx - du/dy); stores
+//             them interleaved for the gathers; forms zeta v, zeta u,
+//             K = (u^2+v^2)/2, eta u, eta v and forward-transforms them along the row.
+//
+// The physical passes carry the depth anomaly eta = h - H instead of the total
+// depth h, and the h accumulators of the three averages integrate eta; H is put
+// back exactly where it enters (H u and H v in the flux divergence, H s in the
+// accumulators, + H in the float64 outputs).  This is the same arithmetic as the
+// total-depth form up to rounding (each average is linear in the averaged field
+// and exact for constants) but keeps the full float32 precision for eta.
+//  rows_rhs   per grid row and task: the Lagrangian-mean right-hand sides in
+//             physical space, then forward row transforms:
+//               XI   : u(x+xi) - w - (w.grad) xi  for both components (eq. (4.5a)),
+//                      w = xi/(t-tau), or u/2 at t = tau
+//               GBAR : f(x+xi) - w.grad g-bar, f in {h, zeta}           (eq. (4.5b))
+//               GTIL : f - u.grad g-tilde                               (eq. (4.1))
+//               P    : (t-tau) u - u.grad P  (inverse lift map, eq. (3.9) in P form)
+//             u(x+xi) and f(x+xi) are periodic bilinear interpolants.
+//  columns    per spectral column kx and prognostic field: forward column
+//             transforms, masked spectral assembly of the right-hand side
+//             (Coriolis, Bernoulli gradient, flux divergence, -nu8 |k|^8), the
+//             classical RK4 update (FP64 for xi and P), and the inverse column
+//             transforms of the next stage's input, ready for the next rows pass.
+//
+// Two real row fields share one complex transform (z = a + i b).
+#pragma once
+
+#include <type_traits>
+
+#include "fft_core.hpp"
+#include "layout.hpp"
+
+namespace lm {
+
+template <typename T>
+struct alignas(4 * sizeof(T)) P4 {
+  T u, v, h, z;
+};
+
+template <typename T>
+struct StepPtrs {
+  cplx<T>* Yr;        // [NSF_R][NKX][NKY] state, working precision
+  cplx<double>* Yd;   // [NSF_D][NKX][NKY] state, float64
+  cplx<T>* Ar;        // RK4 accumulators, same shapes
+  cplx<double>* Ad;
+  cplx<T>* IC;        // [NIC][N][NKXP] column-pass outputs
+  cplx<T>* RS;        // [NRS][N][NKXP] row-pass outputs
+  P4<T>* uvhz;        // [N][N] physical u, v, h, zeta
+  const cplx<T>* tw;  // [N] exp(-2 pi i m / N)
+};
+
+constexpr int ROW_WAVES = 4;  // wavefronts per row-kernel block
+
+__host__ __device__ constexpr int col_tile(int N) {
+  return (N / 16 >= 8) ? 8 : 64 / (N / 16);
+}
+__host__ __device__ constexpr int col_buf(int N) { return padded_len(N) | 1; }
+
+// --------------------------------------------------------------------------
+// row helpers
+// --------------------------------------------------------------------------
+
+// Build lane registers of the length-N spectrum Z = A' + i B' of two real rows
+// from their half spectra A, B (kx = 0..K).  A' = i kx A if DXA (likewise B).
+// Index k = t + NT r; negative kx are the conjugate mirror.
+template <typename T, int N, bool DXA, bool DXB>
+__device__ __forceinline__ void load_pair(cplx<T> (&z)[Plan<N>::E], const cplx<T>* __restrict__ A,
+                                          const cplx<T>* __restrict__ B, int t, int K) {
+  constexpr int E = Plan<N>::E, NT = N / E;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = t + NT * r;
+    int kk;
+    bool mirror;
+    if (k <= K) {
+      kk = k;
+      mirror = false;
+    } else if (k >= N - K) {
+      kk = N - k;
+      mirror = true;
+    } else {
+      z[r] = {T(0), T(0)};
+      continue;
+    }
+    cplx<T> a = A[kk], b = B[kk];
+    if (DXA) a = {-T(kk) * a.y, T(kk) * a.x};
+    if (DXB) b = {-T(kk) * b.y, T(kk) * b.x};
+    if (kk == 0) {
+      a.y = T(0);
+      b.y = T(0);
+    }
+    if (mirror) {
+      a.y = -a.y;
+      b.y = -b.y;
+    }
+    z[r] = {a.x - b.y, a.y + b.x};
+  }
+}
+
+// Inverse-transform a pair and leave lane values p[e] at x = t + NT e.
+template <typename T, int N>
+__device__ __forceinline__ void inverse_row(cplx<T> (&z)[Plan<N>::E], cplx<T>* buf, int t,
+                                            const cplx<T>* __restrict__ tw) {
+  constexpr int E = Plan<N>::E, NT = N / E;
+  fft<T, N, +1>(z, buf, t, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) z[e] = buf[pidx(t + NT * e)];
+  wave_sync();
+}
+
+// Forward-transform z = a + i b (lane values at x = t + NT e) and store the
+// half spectra of a and b (kx = 0..K) to the row pointers OA and OB.
+template <typename T, int N, bool TWO>
+__device__ __forceinline__ void forward_row(cplx<T> (&z)[Plan<N>::E], cplx<T>* buf, int t,
+                                            const cplx<T>* __restrict__ tw, int K,
+                                            cplx<T>* __restrict__ OA, cplx<T>* __restrict__ OB) {
+  constexpr int E = Plan<N>::E, NT = N / E;
+  fft<T, N, -1>(z, buf, t, tw);
+  for (int k = t; k <= K; k += NT) {
+    const cplx<T> zk = buf[pidx(k)];
+    const cplx<T> zm = buf[pidx(k == 0 ? 0 : N - k)];
+    OA[k] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    if (TWO) OB[k] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ int wrapN(int i, int N) { return (i + N) % N; }
+
+// periodic bilinear interpolation of the interleaved physical fields at x + xi
+template <typename T, int N>
+__device__ __forceinline__ P4<T> gather4(const P4<T>* __restrict__ F, int x, int y, T xix, T xiy) {
+  const T scl = T(double(N) / 6.283185307179586476925286766559);
+  T ox = xix * scl, oy = xiy * scl;
+  T fx = floor(ox), fy = floor(oy);
+  // keep indices in range even for non-finite displacements
+  fx = fmin(fmax(fx, T(-N)), T(N));
+  fy = fmin(fmax(fy, T(-N)), T(N));
+  const T ax = ox - fx, ay = oy - fy;
+  const int ix0 = wrapN(x + int(fx), N), iy0 = wrapN(y + int(fy), N);
+  const int ix1 = (ix0 + 1 == N) ? 0 : ix0 + 1, iy1 = (iy0 + 1 == N) ? 0 : iy0 + 1;
+  const P4<T> f00 = F[iy0 * N + ix0], f01 = F[iy0 * N + ix1];
+  const P4<T> f10 = F[iy1 * N + ix0], f11 = F[iy1 * N + ix1];
+  const T w00 = (T(1) - ax) * (T(1) - ay), w01 = ax * (T(1) - ay);
+  const T w10 = (T(1) - ax) * ay, w11 = ax * ay;
+  P4<T> g;
+  g.u = w00 * f00.u + w01 * f01.u + w10 * f10.u + w11 * f11.u;
+  g.v = w00 * f00.v + w01 * f01.v + w10 * f10.v + w11 * f11.v;
+  g.h = w00 * f00.h + w01 * f01.h + w10 * f10.h + w11 * f11.h;
+  g.z = w00 * f00.z + w01 * f01.z + w10 * f10.z + w11 * f11.z;
+  return g;
+}
+
+// --------------------------------------------------------------------------
+// rows_dyn
+// --------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d) {
+  constexpr int E = Plan<N>::E, NT = N / E, PW = 64 / NT, L = padded_len(N);
+  __shared__ cplx<T> lds[ROW_WAVES * PW * L];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / NT, t = lane % NT;
+  const int y = (blockIdx.x * ROW_WAVES + wave) * PW + grp;
+  if (y >= N) return;  // whole wavefronts only (N is a multiple of PW)
+  cplx<T>* buf = lds + (wave * PW + grp) * L;
+  const size_t rf = d.rowfield_elems();
+  const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
+  const int K = d.K;
+
+  cplx<T> uv[E], hz[E];
+  load_pair<T, N, false, false>(uv, ICr + IC_U * rf, ICr + IC_V * rf, t, K);
+  inverse_row<T, N>(uv, buf, t, P.tw);
+  // (eta + i zeta): zeta spectrum = i kx C_v - C_uy
+  {
+    const cplx<T>* Ch = ICr + IC_H * rf;
+    const cplx<T>* Cv = ICr + IC_V * rf;
+    const cplx<T>* Cuy = ICr + IC_UY * rf;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int k = t + NT * r;
+      int kk;
+      bool mirror;
+      if (k <= K) {
+        kk = k;
+        mirror = false;
+      } else if (k >= N - K) {
+        kk = N - k;
+        mirror = true;
+      } else {
+        hz[r] = {T(0), T(0)};
+        continue;
+      }
+      cplx<T> a = Ch[kk];
+      const cplx<T> cv = Cv[kk], cu = Cuy[kk];
+      cplx<T> b = {-T(kk) * cv.y - cu.x, T(kk) * cv.x - cu.y};
+      if (kk == 0) {
+        a.y = T(0);
+        b.y = T(0);
+      }
+      if (mirror) {
+        a.y = -a.y;
+        b.y = -b.y;
+      }
+      hz[r] = {a.x - b.y, a.y + b.x};
+    }
+  }
+  inverse_row<T, N>(hz, buf, t, P.tw);
+
+  P4<T>* out = P.uvhz + (size_t)y * N;
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, hz[e].x, hz[e].y};
+
+  cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
+  cplx<T> z[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
+  forward_row<T, N, true>(z, buf, t, P.tw, K, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    z[e] = {T(0.5) * (uv[e].x * uv[e].x + uv[e].y * uv[e].y), hz[e].x * uv[e].x};  // K, eta u
+  forward_row<T, N, true>(z, buf, t, P.tw, K, RSr + RS_K * rf, RSr + RS_HU * rf);
+#pragma unroll
+  for (int e = 0; e < E; ++e) z[e] = {hz[e].x * uv[e].y, T(0)};  // eta v
+  forward_row<T, N, false>(z, buf, t, P.tw, K, RSr + RS_HV * rf, nullptr);
+}
+
+// --------------------------------------------------------------------------
+// rows_rhs
+// --------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s) {
+  constexpr int E = Plan<N>::E, NT = N / E, PW = 64 / NT, L = padded_len(N);
+  __shared__ cplx<T> lds[ROW_WAVES * PW * L];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / NT, t = lane % NT;
+  const int y = (blockIdx.x * ROW_WAVES + wave) * PW + grp;
+  if (y >= N) return;
+  cplx<T>* buf = lds + (wave * PW + grp) * L;
+  const size_t rf = d.rowfield_elems();
+  const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
+  cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
+  const P4<T>* F = P.uvhz;
+  const P4<T>* Fr = P.uvhz + (size_t)y * N;
+  const int K = d.K;
+  const int task = blockIdx.y;
+
+  cplx<T> a[E], b[E], c[E];
+  if (task == RT_XI || task == RT_GBAR) {
+    // displacement and the partial-mean velocity w
+    load_pair<T, N, false, false>(a, ICr + IC_XIX * rf, ICr + IC_XIY * rf, t, K);
+    inverse_row<T, N>(a, buf, t, P.tw);
+    cplx<T> w[E];
+    if (s > 0.0) {
+      const T inv_s = T(1.0 / s);
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[e] = {a[e].x * inv_s, a[e].y * inv_s};
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const P4<T> q = Fr[t + NT * e];
+        w[e] = {T(0.5) * q.u, T(0.5) * q.v};
+      }
+    }
+    if (task == RT_XI) {
+      load_pair<T, N, true, false>(b, ICr + IC_XIX * rf, ICr + IC_XIX_Y * rf, t, K);
+      inverse_row<T, N>(b, buf, t, P.tw);  // (d xi_x/dx, d xi_x/dy)
+      load_pair<T, N, true, false>(c, ICr + IC_XIY * rf, ICr + IC_XIY_Y * rf, t, K);
+      inverse_row<T, N>(c, buf, t, P.tw);  // (d xi_y/dx, d xi_y/dy)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const P4<T> g = gather4<T, N>(F, t + NT * e, y, a[e].x, a[e].y);
+        const T rx = g.u - w[e].x - (w[e].x * b[e].x + w[e].y * b[e].y);
+        const T ry = g.v - w[e].y - (w[e].x * c[e].x + w[e].y * c[e].y);
+        a[e] = {rx, ry};
+      }
+      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_XIX * rf, RSr + RS_XIY * rf);
+    } else {
+      load_pair<T, N, true, false>(b, ICr + IC_GBH * rf, ICr + IC_GBH_Y * rf, t, K);
+      inverse_row<T, N>(b, buf, t, P.tw);
+      load_pair<T, N, true, false>(c, ICr + IC_GBZ * rf, ICr + IC_GBZ_Y * rf, t, K);
+      inverse_row<T, N>(c, buf, t, P.tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const P4<T> g = gather4<T, N>(F, t + NT * e, y, a[e].x, a[e].y);
+        const T rh = g.h - (w[e].x * b[e].x + w[e].y * b[e].y);
+        const T rz = g.z - (w[e].x * c[e].x + w[e].y * c[e].y);
+        a[e] = {rh, rz};
+      }
+      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_GBH * rf, RSr + RS_GBZ * rf);
+    }
+  } else {
+    const int i1 = (task == RT_GTIL) ? IC_GTH : IC_PX;
+    const int i2 = (task == RT_GTIL) ? IC_GTZ : IC_PY;
+    load_pair<T, N, true, false>(b, ICr + i1 * rf, ICr + (i1 + 1) * rf, t, K);
+    inverse_row<T, N>(b, buf, t, P.tw);
+    load_pair<T, N, true, false>(c, ICr + i2 * rf, ICr + (i2 + 1) * rf, t, K);
+    inverse_row<T, N>(c, buf, t, P.tw);
+    const T sT = T(s);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const P4<T> q = Fr[t + NT * e];
+      const T f1 = (task == RT_GTIL) ? q.h : sT * q.u;
+      const T f2 = (task == RT_GTIL) ? q.z : sT * q.v;
+      a[e] = {f1 - (q.u * b[e].x + q.v * b[e].y), f2 - (q.u * c[e].x + q.v * c[e].y)};
+    }
+    if (task == RT_GTIL)
+      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_GTH * rf, RSr + RS_GTZ * rf);
+    else
+      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_PX * rf, RSr + RS_PY * rf);
+  }
+}
+
+// --------------------------------------------------------------------------
+// columns
+// --------------------------------------------------------------------------
+
+template <typename TS>
+__device__ __forceinline__ cplx<TS> cadd(cplx<TS> a, cplx<TS> b) { return {a.x + b.x, a.y + b.y}; }
+
+// classical RK4: returns the next stage input (the new state after stage 3)
+template <typename TS>
+__device__ __forceinline__ cplx<TS> rk4(int stage, cplx<TS>* __restrict__ Yp, cplx<TS>* __restrict__ Ap,
+                                        cplx<TS> k, double dt) {
+  const cplx<TS> y = *Yp;
+  if (stage == 0) {
+    *Ap = k;
+    const TS c = TS(0.5 * dt);
+    return {y.x + c * k.x, y.y + c * k.y};
+  } else if (stage == 1 || stage == 2) {
+    const cplx<TS> a = *Ap;
+    *Ap = {a.x + TS(2) * k.x, a.y + TS(2) * k.y};
+    const TS c = TS(stage == 1 ? 0.5 * dt : dt);
+    return {y.x + c * k.x, y.y + c * k.y};
+  } else {
+    const cplx<TS> a = *Ap;
+    const TS c = TS(dt / 6.0);
+    const cplx<TS> yn = {y.x + c * (a.x + k.x), y.y + c * (a.y + k.y)};
+    *Yp = yn;
+    return yn;
+  }
+}
+
+template <typename T, int N, int C>
+struct ColCtx {
+  static constexpr int E = Plan<N>::E, NT = N / E, LC = col_buf(N);
+  cplx<T>* lds;     // C buffers of LC
+  cplx<T>* buf;     // this group's buffer
+  int c, t, kx0, kx;
+  bool valid;       // kx <= K
+};
+
+// block-wide: rows of a [N][NKXP] field (columns kx0..kx0+C-1) into the C buffers
+template <typename T, int N, int C>
+__device__ __forceinline__ void tile_load(const ColCtx<T, N, C>& cx, const cplx<T>* __restrict__ src,
+                                          const Dims& d) {
+  constexpr int LC = ColCtx<T, N, C>::LC;
+  __syncthreads();
+  for (int i = threadIdx.x; i < N * C; i += blockDim.x) {
+    const int c = i % C, y = i / C;
+    const int kx = cx.kx0 + c;
+    cplx<T> val = {T(0), T(0)};
+    if (kx <= d.K) val = src[(size_t)y * d.NKXP + kx];
+    cx.lds[c * LC + pidx(y)] = val;
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int C>
+__device__ __forceinline__ void tile_store(const ColCtx<T, N, C>& cx, cplx<T>* __restrict__ dst,
+                                           const Dims& d) {
+  constexpr int LC = ColCtx<T, N, C>::LC;
+  __syncthreads();
+  for (int i = threadIdx.x; i < N * C; i += blockDim.x) {
+    const int c = i % C, y = i / C;
+    const int kx = cx.kx0 + c;
+    if (kx <= d.K) dst[(size_t)y * d.NKXP + kx] = cx.lds[c * LC + pidx(y)];
+  }
+  __syncthreads();
+}
+
+// forward column transform of one row-spectrum field; returns the masked,
+// 1/N^2-normalised right-hand-side values at k = t + NT r
+template <typename T, int N, int C>
+__device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const cplx<T>* src, const Dims& d,
+                                               const cplx<T>* __restrict__ tw, cplx<T> (&out)[Plan<N>::E]) {
+  constexpr int E = Plan<N>::E, NT = N / E;
+  tile_load<T, N, C>(cx, src, d);
+  cplx<T> v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = cx.buf[pidx(cx.t + NT * r)];
+  wave_sync();
+  fft<T, N, -1>(v, cx.buf, cx.t, tw);
+  const T inv = T(1.0 / (double(N) * double(N)));
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const cplx<T> q = cx.buf[pidx(cx.t + NT * r)];
+    out[r] = {q.x * inv, q.y * inv};
+  }
+}
+
+// inverse column transform of values S at k = t + NT r (already zero outside
+// the mask), optionally times i ky, stored to an intermediate field
+template <typename T, int N, int C, typename TS, bool DY>
+__device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const cplx<TS> (&S)[Plan<N>::E],
+                                               cplx<T>* dst, const Dims& d, const cplx<T>* __restrict__ tw) {
+  constexpr int E = Plan<N>::E, NT = N / E;
+  cplx<T> v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = cx.t + NT * r;
+    const int ky = (k <= N / 2) ? k : k - N;
+    cplx<T> q = {T(S[r].x), T(S[r].y)};
+    if (DY) q = {-T(ky) * q.y, T(ky) * q.x};
+    v[r] = q;
+  }
+  __syncthreads();  // the tile buffers may still be read by the previous store
+  fft<T, N, +1>(v, cx.buf, cx.t, tw);
+  tile_store<T, N, C>(cx, dst, d);
+}
+
+template <typename T, int N, int C, int G>
+__device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const StepPtrs<T>& P, const Dims& d,
+                                             const Phys& ph, int stage, const cplx<T>* __restrict__ Ys_in,
+                                             cplx<T>* __restrict__ Ys_out) {
+  constexpr int E = Plan<N>::E, NT = N / E;
+  constexpr bool DBL = (G == CG_XIX || G == CG_XIY || G == CG_PX || G == CG_PY);
+  using TS = typename std::conditional<DBL, double, T>::type;
+  const size_t sp = d.spec_elems();
+  const size_t rf = d.rowfield_elems();
+  const int K = d.K;
+
+  // right-hand-side inputs of this group
+  constexpr int NF = (G == CG_U || G == CG_V || G == CG_H) ? 2 : 1;
+  constexpr int F0 = (G == CG_U) ? RS_ZV : (G == CG_V) ? RS_ZU : (G == CG_H) ? RS_HU
+                   : (G == CG_XIX) ? RS_XIX : (G == CG_XIY) ? RS_XIY : (G == CG_GBH) ? RS_GBH
+                   : (G == CG_GBZ) ? RS_GBZ : (G == CG_GTH) ? RS_GTH : (G == CG_GTZ) ? RS_GTZ
+                   : (G == CG_PX) ? RS_PX : RS_PY;
+  constexpr int F1 = (G == CG_U || G == CG_V) ? RS_K : RS_HV;
+  cplx<T> r0[E], r1[E];
+  if (stage >= 0) {
+    column_forward<T, N, C>(cx, P.RS + F0 * rf, d, P.tw, r0);
+    if constexpr (NF == 2) column_forward<T, N, C>(cx, P.RS + F1 * rf, d, P.tw, r1);
+  }
+
+  // state of this group
+  cplx<TS>* Y;
+  cplx<TS>* A;
+  if constexpr (DBL) {
+    constexpr int sd = (G == CG_XIX) ? SD_XIX : (G == CG_XIY) ? SD_XIY : (G == CG_PX) ? SD_PX : SD_PY;
+    Y = P.Yd + sd * sp;
+    A = P.Ad + sd * sp;
+  } else {
+    constexpr int sr = (G == CG_U) ? SF_U : (G == CG_V) ? SF_V : (G == CG_H) ? SF_H : (G == CG_GBH) ? SF_GBH
+                     : (G == CG_GBZ) ? SF_GBZ : (G == CG_GTH) ? SF_GTH : SF_GTZ;
+    Y = reinterpret_cast<cplx<TS>*>(P.Yr) + sr * sp;
+    A = reinterpret_cast<cplx<TS>*>(P.Ar) + sr * sp;
+  }
+  const size_t col = (size_t)cx.kx * d.NKY;
+  const T fT = T(ph.f), gT = T(ph.g);
+
+  cplx<TS> S[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = cx.t + NT * r;
+    int ky;
+    bool in = true;
+    if (k <= K) ky = k;
+    else if (k >= N - K) ky = k - N;
+    else { ky = 0; in = false; }
+    S[r] = {TS(0), TS(0)};
+    if (!(in && cx.valid)) continue;
+    const size_t j = col + (size_t)(ky + K);
+    if (stage < 0) {
+      S[r] = Y[j];
+      if constexpr (G == CG_U || G == CG_V || G == CG_H) Ys_out[(G - CG_U) * sp + j] = S[r];
+      continue;
+    }
+    const T kxT = T(cx.kx), kyT = T(ky);
+    const double k2 = double(cx.kx) * cx.kx + double(ky) * ky;
+    const T hv = T(ph.nu8 * (k2 * k2) * (k2 * k2));
+    cplx<T> R;
+    if constexpr (G == CG_U) {
+      // zeta v + f v - i kx (g h + K) - nu8 |k|^8 u
+      const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
+      const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
+      R = {r0[r].x + fT * v.x + kxT * B.y - hv * u.x, r0[r].y + fT * v.y - kxT * B.x - hv * u.y};
+    } else if constexpr (G == CG_V) {
+      // -zeta u - f u - i ky (g h + K) - nu8 |k|^8 v
+      const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
+      const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
+      R = {-r0[r].x - fT * u.x + kyT * B.y - hv * v.x, -r0[r].y - fT * u.y - kyT * B.x - hv * v.y};
+    } else if constexpr (G == CG_H) {
+      // -i kx (H u + F(eta u)) - i ky (H v + F(eta v)) - nu8 |k|^8 h
+      const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
+      const T HT = T(ph.H);
+      const cplx<T> fx = {HT * u.x + r0[r].x, HT * u.y + r0[r].y};
+      const cplx<T> fy = {HT * v.x + r1[r].x, HT * v.y + r1[r].y};
+      R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
+      // Eulerian accumulators: dE_eta/dt = eta (h less H at k = 0), dE_zeta/dt = i kx v - i ky u
+      cplx<T>* Yr = P.Yr;
+      cplx<T>* Ar = P.Ar;
+      cplx<T> eta = h;
+      if (cx.kx == 0 && ky == 0) eta.x -= HT;
+      rk4<T>(stage, Yr + SF_EH * sp + j, Ar + SF_EH * sp + j, eta, ph.dt);
+      const cplx<T> zeta = {-kxT * v.y + kyT * u.y, kxT * v.x - kyT * u.x};
+      rk4<T>(stage, Yr + SF_EZ * sp + j, Ar + SF_EZ * sp + j, zeta, ph.dt);
+    } else {
+      R = r0[r];
+    }
+    const cplx<TS> Rk = {TS(R.x), TS(R.y)};
+    S[r] = rk4<TS>(stage, Y + j, A + j, Rk, ph.dt);
+    if constexpr (G == CG_U || G == CG_V || G == CG_H) Ys_out[(G - CG_U) * sp + j] = S[r];
+  }
+
+  // inverse column transforms of the next stage input
+  if constexpr (G == CG_U) {
+    column_inverse<T, N, C, TS, false>(cx, S, P.IC + IC_U * rf, d, P.tw);
+    column_inverse<T, N, C, TS, true>(cx, S, P.IC + IC_UY * rf, d, P.tw);
+  } else if constexpr (G == CG_V) {
+    column_inverse<T, N, C, TS, false>(cx, S, P.IC + IC_V * rf, d, P.tw);
+  } else if constexpr (G == CG_H) {
+    // the rows passes work with eta = h - H: drop H from the mean (k = 0, lane 0)
+    if (cx.kx == 0 && cx.t == 0) S[0].x -= TS(ph.H);
+    column_inverse<T, N, C, TS, false>(cx, S, P.IC + IC_H * rf, d, P.tw);
+  } else {
+    constexpr int o = (G == CG_XIX) ? IC_XIX : (G == CG_XIY) ? IC_XIY : (G == CG_GBH) ? IC_GBH
+                    : (G == CG_GBZ) ? IC_GBZ : (G == CG_GTH) ? IC_GTH : (G == CG_GTZ) ? IC_GTZ
+                    : (G == CG_PX) ? IC_PX : IC_PY;
+    column_inverse<T, N, C, TS, false>(cx, S, P.IC + o * rf, d, P.tw);
+    column_inverse<T, N, C, TS, true>(cx, S, P.IC + (o + 1) * rf, d, P.tw);
+  }
+}
+
+// stage >= 0: RK4 stage; stage < 0: only transform the current state (prologue)
+template <typename T, int N>
+__global__ void __launch_bounds__(col_tile(N) * (N / 16))
+    k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out) {
+  constexpr int C = col_tile(N);
+  constexpr int E = Plan<N>::E, NT = N / E, LC = col_buf(N);
+  __shared__ cplx<T> lds[C * LC];
+  ColCtx<T, N, C> cx;
+  cx.lds = lds;
+  cx.c = threadIdx.x / NT;
+  cx.t = threadIdx.x % NT;
+  cx.buf = lds + cx.c * LC;
+  cx.kx0 = blockIdx.x * C;
+  cx.kx = cx.kx0 + cx.c;
+  cx.valid = cx.kx <= d.K;
+  switch (blockIdx.y) {
+    case CG_U: column_group<T, N, C, CG_U>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_V: column_group<T, N, C, CG_V>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_H: column_group<T, N, C, CG_H>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_XIX: column_group<T, N, C, CG_XIX>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_XIY: column_group<T, N, C, CG_XIY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_GBH: column_group<T, N, C, CG_GBH>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_GBZ: column_group<T, N, C, CG_GBZ>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_GTH: column_group<T, N, C, CG_GTH>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_GTZ: column_group<T, N, C, CG_GTZ>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_PX: column_group<T, N, C, CG_PX>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_PY: column_group<T, N, C, CG_PY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    default: break;
+  }
+}
+
+}  // namespace lm

@@ -1,0 +1,205 @@
+"""ctypes binding of liblagmean.so (include/lagmean.h); argument marshalling only.
+
+Every computation happens in the HIP library.  Arrays may be NumPy float64
+arrays (host) or torch CUDA float64 tensors (device); PyTorch is only used for
+device memory and streams.  Importing this module fails loudly when the library
+has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblagmean.so")
+
+LM_OK = 0
+STATUS = {0: "LM_OK", -1: "LM_E_ARG", -2: "LM_E_STATE", -3: "LM_E_OOM", -4: "LM_E_HIP",
+          -5: "LM_E_NONFINITE", -6: "LM_E_UNSUPPORTED", -7: "LM_E_BUDGET"}
+LM_FP64, LM_FP32_MIXED = 0, 1
+LM_K_S2_MEAN, LM_K_S2_XI_X, LM_K_S2_XI_Y, LM_K_S1_MEAN, LM_K_S1_ETA_X, LM_K_S1_ETA_Y, LM_K_EULER_MEAN = range(7)
+LM_FIELD_H, LM_FIELD_ZETA = 0, 1
+PEEK = {"u": 0, "v": 1, "h": 2, "gbar:h": 3, "gbar:zeta": 4, "gtil:h": 5, "gtil:zeta": 6,
+        "E:h": 7, "E:zeta": 8, "xi_x": 9, "xi_y": 10, "P_x": 11, "P_y": 12}
+# output names (the oracle's naming) -> (field, kind)
+OUTPUTS = {
+    "S2_mean:h": (LM_FIELD_H, LM_K_S2_MEAN), "S2_mean:zeta": (LM_FIELD_ZETA, LM_K_S2_MEAN),
+    "S2_xi_x": (0, LM_K_S2_XI_X), "S2_xi_y": (0, LM_K_S2_XI_Y),
+    "S1_mean:h": (LM_FIELD_H, LM_K_S1_MEAN), "S1_mean:zeta": (LM_FIELD_ZETA, LM_K_S1_MEAN),
+    "S1_eta_x": (0, LM_K_S1_ETA_X), "S1_eta_y": (0, LM_K_S1_ETA_Y),
+    "E_mean:h": (LM_FIELD_H, LM_K_EULER_MEAN), "E_mean:zeta": (LM_FIELD_ZETA, LM_K_EULER_MEAN),
+}
+
+
+class LagMeanError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("f", ctypes.c_double), ("g", ctypes.c_double), ("H", ctypes.c_double),
+                ("dt", ctypes.c_double), ("nu8", ctypes.c_double),
+                ("avg_fields", ctypes.c_uint32), ("strategies", ctypes.c_uint32),
+                ("interp", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2208_02682_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    D = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lm_query_footprint": [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)],
+        "lm_create": [ctypes.POINTER(Config), P, ctypes.POINTER(P)],
+        "lm_set_state": [P, P, P, P, ctypes.c_int],
+        "lm_get_state": [P, P, P, P, ctypes.c_int],
+        "lm_begin_interval": [P],
+        "lm_step": [P, ctypes.c_int32],
+        "lm_step_profiled": [P, ctypes.c_int32, D],
+        "lm_end_interval": [P, D],
+        "lm_read_mean": [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int],
+        "lm_peek": [P, ctypes.c_int32, P, ctypes.c_int],
+        "lm_counters": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+        "lm_destroy": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.lm_status_str.argtypes = [ctypes.c_int]
+    lib.lm_status_str.restype = ctypes.c_char_p
+    lib.lm_last_error.argtypes = []
+    lib.lm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != LM_OK:
+        msg = load_library().lm_last_error().decode()
+        raise LagMeanError(status, msg)
+
+
+def make_config(n: int, *, precision: str = "fp64", f: float = 1.0, g: float = 1.0, H: float = 1.0,
+                dt: float, nu8: float = 0.0) -> Config:
+    prec = {"fp64": LM_FP64, "fp32": LM_FP32_MIXED}[precision]
+    return Config(n=n, precision=prec, f=f, g=g, H=H, dt=dt, nu8=nu8, avg_fields=0, strategies=0,
+                  interp=0, mode=0)
+
+
+def footprint(cfg: Config) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().lm_query_footprint(ctypes.byref(cfg), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _is_device(a) -> bool:
+    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _ptr(a):
+    if _is_device(a):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _host_in(a, N):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (N, N):
+        raise ValueError(f"expected an {N}x{N} array, got {a.shape}")
+    return a
+
+
+class Run:
+    """One averaging run on the GPU (wraps lm_run)."""
+
+    def __init__(self, cfg: Config, stream: int = 0):
+        self.lib = load_library()
+        self.cfg = cfg
+        self.N = cfg.n
+        self.h = ctypes.c_void_p(0)
+        _check(self.lib.lm_create(ctypes.byref(cfg), ctypes.c_void_p(stream), ctypes.byref(self.h)))
+
+    # -- lifetime
+    def close(self) -> None:
+        if self.h and self.h.value:
+            _check(self.lib.lm_destroy(self.h))
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state
+    def set_state(self, u, v, h) -> None:
+        if _is_device(u):
+            for a in (u, v, h):
+                if a.dtype.__str__() != "torch.float64" or not a.is_contiguous() or tuple(a.shape) != (self.N, self.N):
+                    raise ValueError("device inputs must be contiguous float64 N x N tensors")
+            _check(self.lib.lm_set_state(self.h, _ptr(u), _ptr(v), _ptr(h), 1))
+        else:
+            u, v, h = (_host_in(a, self.N) for a in (u, v, h))
+            _check(self.lib.lm_set_state(self.h, _ptr(u), _ptr(v), _ptr(h), 0))
+
+    def get_state(self):
+        out = [np.empty((self.N, self.N)) for _ in range(3)]
+        _check(self.lib.lm_get_state(self.h, *(_ptr(a) for a in out), 0))
+        return tuple(out)
+
+    # -- averaging
+    def begin_interval(self) -> None:
+        _check(self.lib.lm_begin_interval(self.h))
+
+    def step(self, nsteps: int = 1) -> None:
+        _check(self.lib.lm_step(self.h, int(nsteps)))
+
+    def step_profiled(self, nsteps: int):
+        """Average milliseconds of (rows_dyn, rows_rhs, columns) over nsteps steps."""
+        ms = (ctypes.c_double * 3)()
+        _check(self.lib.lm_step_profiled(self.h, int(nsteps), ms))
+        return list(ms)
+
+    def end_interval(self) -> float:
+        T = ctypes.c_double(0.0)
+        _check(self.lib.lm_end_interval(self.h, ctypes.byref(T)))
+        return T.value
+
+    def read_mean(self, field: int, kind: int, out=None):
+        if out is None:
+            out = np.empty((self.N, self.N))
+        _check(self.lib.lm_read_mean(self.h, field, kind, _ptr(out), 1 if _is_device(out) else 0))
+        return out
+
+    def outputs(self) -> Dict[str, np.ndarray]:
+        return {name: self.read_mean(fk[0], fk[1]) for name, fk in OUTPUTS.items()}
+
+    def peek(self, which: str):
+        out = np.empty((self.N, self.N))
+        _check(self.lib.lm_peek(self.h, PEEK[which], _ptr(out), 0))
+        return out
+
+    def counters(self):
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(self.lib.lm_counters(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
