@@ -83,6 +83,9 @@ def main(argv=None) -> int:
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (the method's runs are independent per GPU); "
@@ -91,6 +94,15 @@ def main(argv=None) -> int:
 
     import numpy as np
     import torch
+    if a.copy_probe:
+        n = a.copy_probe * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 4, "repeats": 5}), flush=True)
+        return 0
     from paper_2208_02682_amd import Run, make_config
     from synth import workload
 

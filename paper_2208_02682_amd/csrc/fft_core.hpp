@@ -1,13 +1,13 @@
-// Batched 1-D complex FFTs held by groups of lanes of one wavefront (gfx950).
+// Batched 1-D complex FFTs held by groups of lanes (gfx950, 64-wide wavefronts).
 //
-// An N-point transform is owned by NT = N / E consecutive lanes of a single
-// 64-wide wavefront; lane t of the group holds E complex values.  On entry lane t
-// holds x[t + NT * e] in v[e] (e = 0..E-1).  The first Stockham stage is a
-// radix-E DFT done in registers; later stages (radices R dividing E, each lane
-// doing E/R butterflies) exchange data through the group's private LDS buffer.
-// On exit the spectrum is in the LDS buffer in natural order (padded indexing).
-// Because a group never spans two wavefronts, the exchanges only need
-// wavefront-scope ordering, never a workgroup barrier.
+// An N-point transform is owned by NT = N / E consecutive lanes; lane t of the
+// group holds E complex values.  On entry lane t holds x[t + NT * e] in v[e]
+// (e = 0..E-1).  The first Stockham stage is a radix-E DFT done in registers;
+// later stages (radices R dividing E, each lane doing E/R butterflies) exchange
+// data through the group's private LDS buffer.  On exit the spectrum is in the
+// LDS buffer in natural order (padded indexing).  When a group fits in one
+// wavefront (NT <= 64) the exchanges only need wavefront-scope ordering;
+// otherwise they use workgroup barriers.
 //
 // Stockham autosort formulation (decimation in time): at a stage with radix R
 // applied after sub-transforms of length Ns, butterfly j (0 <= j < N/R) reads
@@ -56,6 +56,10 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// keeps the instruction scheduler from moving work (in particular global loads)
+// across phase boundaries, which would keep many loads in flight in registers
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 // padded LDS index: one spare complex slot every 16 spreads strided accesses
 // over the banks
@@ -162,32 +166,43 @@ __device__ __forceinline__ void dft(cplx<T>* v) {
 }
 
 // ---------------------------------------------------------------------------
-// plans: E values per lane and the radices after the first (radix-E) stage
+// plans: N = E * R2 * R3 * R4 with E values per lane; the first stage is a
+// radix-E DFT in registers, the later radices divide E
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int E>
 struct Plan;
-template <> struct Plan<16>   { static constexpr int E = 16; static constexpr int R2 = 1,  R3 = 1; };
-template <> struct Plan<32>   { static constexpr int E = 16; static constexpr int R2 = 2,  R3 = 1; };
-template <> struct Plan<64>   { static constexpr int E = 16; static constexpr int R2 = 4,  R3 = 1; };
-template <> struct Plan<128>  { static constexpr int E = 16; static constexpr int R2 = 8,  R3 = 1; };
-template <> struct Plan<256>  { static constexpr int E = 16; static constexpr int R2 = 16, R3 = 1; };
-template <> struct Plan<512>  { static constexpr int E = 16; static constexpr int R2 = 16, R3 = 2; };
-template <> struct Plan<1024> { static constexpr int E = 16; static constexpr int R2 = 16, R3 = 4; };
+template <> struct Plan<16, 16>   { static constexpr int R2 = 1,  R3 = 1, R4 = 1; };
+template <> struct Plan<32, 16>   { static constexpr int R2 = 2,  R3 = 1, R4 = 1; };
+template <> struct Plan<64, 16>   { static constexpr int R2 = 4,  R3 = 1, R4 = 1; };
+template <> struct Plan<128, 16>  { static constexpr int R2 = 8,  R3 = 1, R4 = 1; };
+template <> struct Plan<256, 16>  { static constexpr int R2 = 16, R3 = 1, R4 = 1; };
+template <> struct Plan<512, 16>  { static constexpr int R2 = 16, R3 = 2, R4 = 1; };
+template <> struct Plan<1024, 16> { static constexpr int R2 = 16, R3 = 4, R4 = 1; };
+template <> struct Plan<64, 8>    { static constexpr int R2 = 8,  R3 = 1, R4 = 1; };
+template <> struct Plan<128, 8>   { static constexpr int R2 = 8,  R3 = 2, R4 = 1; };
+template <> struct Plan<256, 8>   { static constexpr int R2 = 8,  R3 = 4, R4 = 1; };
+template <> struct Plan<512, 8>   { static constexpr int R2 = 8,  R3 = 8, R4 = 1; };
+template <> struct Plan<1024, 8>  { static constexpr int R2 = 8,  R3 = 8, R4 = 2; };
 
-template <int N>
-struct FFTShape {
-  static constexpr int E = Plan<N>::E;
-  static constexpr int NT = N / E;          // lanes per transform
-  static constexpr int PER_WAVE = 64 / NT;  // transforms per wavefront
-  static constexpr int LDS = padded_len(N); // complex slots per transform buffer
-  static_assert(NT <= 64, "a transform must fit in one wavefront");
-};
+// values per lane of the column and row passes.  16 keeps a 1024-point
+// transform inside one wavefront (no workgroup barriers); measured on the
+// 1024^2 workload it beats 8 values per lane (which halves the registers but
+// needs a barrier per exchange) by about 25% in the row passes.
+constexpr int COL_E = 16;
+constexpr int ROW_E = 16;
+
+// exchanges of a transform owned by NT lanes: wavefront-scope ordering when the
+// transform lives in one wavefront, a workgroup barrier otherwise
+template <int NT>
+__device__ __forceinline__ void xsync() {
+  if constexpr (NT > 64) __syncthreads();
+  else wave_sync();
+}
 
 // one Stockham stage of radix R after sub-transforms of length Ns (Ns > 1),
 // reading and writing the group's LDS buffer
-template <typename T, int N, int DIR, int Ns, int R>
+template <typename T, int N, int E, int DIR, int Ns, int R>
 __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, const cplx<T>* __restrict__ tw) {
-  constexpr int E = Plan<N>::E;
   constexpr int NT = N / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide E");
@@ -198,7 +213,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, const cplx<T
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b * R + r] = buf[pidx(j + r * (N / R))];
   }
-  wave_sync();
+  xsync<NT>();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = t + b * NT;
@@ -213,21 +228,27 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, const cplx<T
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[pidx(base + r * Ns)] = v[b * R + r];
   }
-  wave_sync();
+  xsync<NT>();
 }
 
-// Full transform.  v: lane data x[t + NT e]; buf: the group's LDS buffer.
-// DIR = -1: forward (exp(-i...)), DIR = +1: inverse (unnormalised).
-template <typename T, int N, int DIR>
-__device__ __forceinline__ void fft(cplx<T> (&v)[Plan<N>::E], cplx<T>* buf, int t,
-                                    const cplx<T>* __restrict__ tw) {
-  constexpr int E = Plan<N>::E;
+// Full transform of N points held by NT = N / E lanes.  v: lane t holds
+// x[t + NT e]; buf: the group's LDS buffer (padded_len(N) slots).  On exit the
+// spectrum is in buf in natural order.  DIR = -1: forward (exp(-i...)),
+// DIR = +1: inverse (unnormalised).
+template <typename T, int N, int E, int DIR>
+__device__ __forceinline__ void fft(cplx<T> (&v)[E], cplx<T>* buf, int t, const cplx<T>* __restrict__ tw) {
+  using PL = Plan<N, E>;
+  constexpr int NT = N / E;
+  // a fresh view of the twiddle table for every transform: stops the compiler
+  // from keeping twiddles of one transform live until the next one
+  asm volatile("" : "+s"(tw));
   dft<E, DIR>(v);
 #pragma unroll
   for (int r = 0; r < E; ++r) buf[pidx(t * E + r)] = v[r];
-  wave_sync();
-  if constexpr (Plan<N>::R2 > 1) stockham_stage<T, N, DIR, E, Plan<N>::R2>(buf, t, tw);
-  if constexpr (Plan<N>::R3 > 1) stockham_stage<T, N, DIR, E * Plan<N>::R2, Plan<N>::R3>(buf, t, tw);
+  xsync<NT>();
+  if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, tw);
+  if constexpr (PL::R3 > 1) stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, tw);
+  if constexpr (PL::R4 > 1) stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, tw);
 }
 
 }  // namespace lm

@@ -10,13 +10,12 @@ namespace lm {
 
 template <int N>
 __global__ void __launch_bounds__(64 * ROW_WAVES) k_io_row_forward(IoRowFwd J, Dims d, const cplx<double>* tw) {
-  constexpr int E = Plan<N>::E, NT = N / E, PW = 64 / NT, L = padded_len(N);
-  __shared__ cplx<double> lds[ROW_WAVES * PW * L];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / NT, t = lane % NT;
-  const int y = (blockIdx.x * ROW_WAVES + wave) * PW + grp;
-  if (y >= N) return;
-  cplx<double>* buf = lds + (wave * PW + grp) * L;
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT;
+  __shared__ cplx<double> lds[G::RPB * G::L];
+  const int grp = row_group<NT>(), t = threadIdx.x % NT;
+  const int y = blockIdx.x * G::RPB + grp;
+  cplx<double>* buf = lds + grp * G::L;
   const int q = blockIdx.y;
   cplx<double> z[E];
 #pragma unroll
@@ -27,26 +26,25 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_io_row_forward(IoRowFwd J, D
   cplx<double>* OA = J.oa[q] + (size_t)y * d.NKXP;
   if (J.b[q]) {
     cplx<double>* OB = J.ob[q] + (size_t)y * d.NKXP;
-    forward_row<double, N, true>(z, buf, t, tw, d.K, OA, OB);
+    forward_row<double, N, true>(z, buf, t, tw, OA, OB);
   } else {
-    forward_row<double, N, false>(z, buf, t, tw, d.K, OA, nullptr);
+    forward_row<double, N, false>(z, buf, t, tw, OA, nullptr);
   }
 }
 
 template <int N>
 __global__ void __launch_bounds__(64 * ROW_WAVES) k_io_row_inverse(IoRowInv J, Dims d, const cplx<double>* tw) {
-  constexpr int E = Plan<N>::E, NT = N / E, PW = 64 / NT, L = padded_len(N);
-  __shared__ cplx<double> lds[ROW_WAVES * PW * L];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / NT, t = lane % NT;
-  const int y = (blockIdx.x * ROW_WAVES + wave) * PW + grp;
-  if (y >= N) return;
-  cplx<double>* buf = lds + (wave * PW + grp) * L;
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT;
+  __shared__ cplx<double> lds[G::RPB * G::L];
+  const int grp = row_group<NT>(), t = threadIdx.x % NT;
+  const int y = blockIdx.x * G::RPB + grp;
+  cplx<double>* buf = lds + grp * G::L;
   const int q = blockIdx.y;
   const cplx<double>* A = J.a[q] + (size_t)y * d.NKXP;
   const cplx<double>* B = J.b[q] ? J.b[q] + (size_t)y * d.NKXP : A;
   cplx<double> z[E];
-  load_pair<double, N, false, false>(z, A, B, t, d.K);
+  load_pair<double, N, false, false>(z, A, B, t);
   inverse_row<double, N>(z, buf, t, tw);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -60,7 +58,7 @@ template <int N>
 __global__ void __launch_bounds__(col_tile(N) * (N / 16))
     k_io_col_forward(IoColFwd J, Dims d, const cplx<double>* tw) {
   constexpr int C = col_tile(N);
-  constexpr int E = Plan<N>::E, NT = N / E, LC = col_buf(N);
+  constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
   __shared__ cplx<double> lds[C * LC];
   ColCtx<double, N, C> cx;
   cx.lds = lds;
@@ -69,7 +67,7 @@ __global__ void __launch_bounds__(col_tile(N) * (N / 16))
   cx.buf = lds + cx.c * LC;
   cx.kx0 = blockIdx.x * C;
   cx.kx = cx.kx0 + cx.c;
-  cx.valid = cx.kx <= d.K;
+  cx.valid = cx.kx <= kcut<N>();
   const int q = blockIdx.y;
   cplx<double> out[E];
   column_forward<double, N, C>(cx, J.src[q], d, tw, out);
@@ -79,8 +77,8 @@ __global__ void __launch_bounds__(col_tile(N) * (N / 16))
   for (int r = 0; r < E; ++r) {
     const int k = cx.t + NT * r;
     int ky;
-    if (k <= d.K) ky = k;
-    else if (k >= N - d.K) ky = k - N;
+    if (k <= kcut<N>()) ky = k;
+    else if (k >= N - kcut<N>()) ky = k - N;
     else continue;
     const size_t j = col + (size_t)(ky + d.K);
     cplx<double> v = out[r];
@@ -94,7 +92,7 @@ template <int N>
 __global__ void __launch_bounds__(col_tile(N) * (N / 16))
     k_io_col_inverse(IoColInv J, Dims d, const cplx<double>* tw) {
   constexpr int C = col_tile(N);
-  constexpr int E = Plan<N>::E, NT = N / E, LC = col_buf(N);
+  constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
   __shared__ cplx<double> lds[C * LC];
   ColCtx<double, N, C> cx;
   cx.lds = lds;
@@ -103,7 +101,7 @@ __global__ void __launch_bounds__(col_tile(N) * (N / 16))
   cx.buf = lds + cx.c * LC;
   cx.kx0 = blockIdx.x * C;
   cx.kx = cx.kx0 + cx.c;
-  cx.valid = cx.kx <= d.K;
+  cx.valid = cx.kx <= kcut<N>();
   const int q = blockIdx.y;
   const size_t col = (size_t)cx.kx * d.NKY;
   cplx<double> S[E];
@@ -112,8 +110,8 @@ __global__ void __launch_bounds__(col_tile(N) * (N / 16))
     const int k = cx.t + NT * r;
     int ky;
     S[r] = {0.0, 0.0};
-    if (k <= d.K) ky = k;
-    else if (k >= N - d.K) ky = k - N;
+    if (k <= kcut<N>()) ky = k;
+    else if (k >= N - kcut<N>()) ky = k - N;
     else continue;
     if (!cx.valid) continue;
     const size_t j = col + (size_t)(ky + d.K);

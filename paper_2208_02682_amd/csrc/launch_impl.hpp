@@ -25,9 +25,7 @@ StepPtrs<T> step_ptrs(RunView& r) {
 
 template <int N>
 dim3 row_grid(int tasks) {
-  constexpr int PW = 64 / (N / 16);
-  constexpr int rows = ROW_WAVES * PW;
-  return dim3((N + rows - 1) / rows, tasks);
+  return dim3(N / RowGeo<N>::RPB, tasks);
 }
 template <int N>
 dim3 col_grid(const Dims& d, int groups) {

@@ -55,7 +55,11 @@ enum ColGroup : int {
 };
 
 // row-kernel tasks of the right-hand-side pass
-enum RowTask : int { RT_XI = 0, RT_GBAR, RT_GTIL, RT_P, NRT = 4 };
+enum RowTask : int { RT_XI = 0, RT_GB, RT_GT, RT_P, NRT = 4 };
+
+// 2/3-rule cutoff: modes |kx|, |ky| <= K are kept (a compile-time constant of N)
+template <int N>
+__host__ __device__ constexpr int kcut() { return (N - 1) / 3; }
 
 struct Dims {
   int N, K, NKX, NKY, NKXP;

@@ -13,13 +13,13 @@
 // accumulators, + H in the float64 outputs).  This is the same arithmetic as the
 // total-depth form up to rounding (each average is linear in the averaged field
 // and exact for constants) but keeps the full float32 precision for eta.
-//  rows_rhs   per grid row and task: the Lagrangian-mean right-hand sides in
-//             physical space, then forward row transforms:
-//               XI   : u(x+xi) - w - (w.grad) xi  for both components (eq. (4.5a)),
-//                      w = xi/(t-tau), or u/2 at t = tau
-//               GBAR : f(x+xi) - w.grad g-bar, f in {h, zeta}           (eq. (4.5b))
-//               GTIL : f - u.grad g-tilde                               (eq. (4.1))
-//               P    : (t-tau) u - u.grad P  (inverse lift map, eq. (3.9) in P form)
+//  rows_rhs   per grid row and strategy: the Lagrangian-mean right-hand sides
+//             in physical space, then forward row transforms:
+//               S2: u(x+xi) - w - (w.grad) xi  for both components (eq. (4.5a)),
+//                   w = xi/(t-tau), or u/2 at t = tau, and
+//                   f(x+xi) - w.grad g-bar, f in {h, zeta}             (eq. (4.5b));
+//               S1: f - u.grad g-tilde                                 (eq. (4.1)) and
+//                   (t-tau) u - u.grad P  (inverse lift map, eq. (3.9) in P form).
 //             u(x+xi) and f(x+xi) are periodic bilinear interpolants.
 //  columns    per spectral column kx and prognostic field: forward column
 //             transforms, masked spectral assembly of the right-hand side
@@ -56,6 +56,22 @@ struct StepPtrs {
 
 constexpr int ROW_WAVES = 4;  // wavefronts per row-kernel block
 
+// row kernels: one lane group of NT = N / ROW_E lanes per grid row
+template <int N>
+struct RowGeo {
+  static constexpr int E = ROW_E, NT = N / E;
+  static constexpr int RPB = 64 * ROW_WAVES / NT;  // rows per block
+  static constexpr int L = padded_len(N);           // LDS slots per row
+  static_assert(RPB >= 1 && N % RPB == 0, "row geometry");
+};
+
+// group index (uniform per wavefront when a group spans whole wavefronts)
+template <int NT>
+__device__ __forceinline__ int row_group() {
+  if constexpr (NT >= 64) return __builtin_amdgcn_readfirstlane(threadIdx.x / NT);
+  else return threadIdx.x / NT;
+}
+
 __host__ __device__ constexpr int col_tile(int N) {
   return (N / 16 >= 8) ? 8 : 64 / (N / 16);
 }
@@ -69,68 +85,75 @@ __host__ __device__ constexpr int col_buf(int N) { return padded_len(N) | 1; }
 // from their half spectra A, B (kx = 0..K).  A' = i kx A if DXA (likewise B).
 // Index k = t + NT r; negative kx are the conjugate mirror.
 template <typename T, int N, bool DXA, bool DXB>
-__device__ __forceinline__ void load_pair(cplx<T> (&z)[Plan<N>::E], const cplx<T>* __restrict__ A,
-                                          const cplx<T>* __restrict__ B, int t, int K) {
-  constexpr int E = Plan<N>::E, NT = N / E;
+__device__ __forceinline__ void load_pair(cplx<T> (&z)[ROW_E], const cplx<T>* __restrict__ A,
+                                          const cplx<T>* __restrict__ B, int t) {
+  constexpr int E = ROW_E, NT = N / E, K = kcut<N>();
+  sched_fence();
+  // branch-free: every lane loads (a clamped index where the mask is empty) and
+  // selects, so the unrolled loop has no lane-divergent control flow
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int k = t + NT * r;
-    int kk;
-    bool mirror;
-    if (k <= K) {
-      kk = k;
-      mirror = false;
-    } else if (k >= N - K) {
-      kk = N - k;
-      mirror = true;
-    } else {
-      z[r] = {T(0), T(0)};
-      continue;
-    }
+    const bool lo = k <= K, hi = k >= N - K;
+    const int kk = min(lo ? k : N - k, K);
     cplx<T> a = A[kk], b = B[kk];
     if (DXA) a = {-T(kk) * a.y, T(kk) * a.x};
     if (DXB) b = {-T(kk) * b.y, T(kk) * b.x};
-    if (kk == 0) {
-      a.y = T(0);
-      b.y = T(0);
-    }
-    if (mirror) {
-      a.y = -a.y;
-      b.y = -b.y;
-    }
-    z[r] = {a.x - b.y, a.y + b.x};
+    const T sy = (kk == 0) ? T(0) : (hi ? T(-1) : T(1));  // real at kx = 0, conjugate mirror
+    a.y *= sy;
+    b.y *= sy;
+    z[r] = (lo || hi) ? cplx<T>{a.x - b.y, a.y + b.x} : cplx<T>{T(0), T(0)};
   }
 }
 
 // Inverse-transform a pair and leave lane values p[e] at x = t + NT e.
 template <typename T, int N>
-__device__ __forceinline__ void inverse_row(cplx<T> (&z)[Plan<N>::E], cplx<T>* buf, int t,
+__device__ __forceinline__ void inverse_row(cplx<T> (&z)[ROW_E], cplx<T>* buf, int t,
                                             const cplx<T>* __restrict__ tw) {
-  constexpr int E = Plan<N>::E, NT = N / E;
-  fft<T, N, +1>(z, buf, t, tw);
+  constexpr int E = ROW_E, NT = N / E;
+  fft<T, N, E, +1>(z, buf, t, tw);
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = buf[pidx(t + NT * e)];
-  wave_sync();
+  xsync<NT>();
+  sched_fence();
 }
 
 // Forward-transform z = a + i b (lane values at x = t + NT e) and store the
 // half spectra of a and b (kx = 0..K) to the row pointers OA and OB.
 template <typename T, int N, bool TWO>
-__device__ __forceinline__ void forward_row(cplx<T> (&z)[Plan<N>::E], cplx<T>* buf, int t,
-                                            const cplx<T>* __restrict__ tw, int K,
+__device__ __forceinline__ void forward_row(cplx<T> (&z)[ROW_E], cplx<T>* buf, int t,
+                                            const cplx<T>* __restrict__ tw,
                                             cplx<T>* __restrict__ OA, cplx<T>* __restrict__ OB) {
-  constexpr int E = Plan<N>::E, NT = N / E;
-  fft<T, N, -1>(z, buf, t, tw);
+  constexpr int E = ROW_E, NT = N / E, K = kcut<N>();
+  fft<T, N, E, -1>(z, buf, t, tw);
   for (int k = t; k <= K; k += NT) {
     const cplx<T> zk = buf[pidx(k)];
     const cplx<T> zm = buf[pidx(k == 0 ? 0 : N - k)];
     OA[k] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     if (TWO) OB[k] = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
   }
-  wave_sync();
+  xsync<NT>();
+  sched_fence();
 }
 
 __device__ __forceinline__ int wrapN(int i, int N) { return (i + N) % N; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Renumber the flattened block index so that every XCD receives a contiguous
+// run of logical blocks, and split the logical index with the task (or field
+// group) fastest: each XCD then gets an even mix of heavy and light tasks, and
+// all tasks of neighbouring rows / column tiles meet in the same L2 (the
+// gathers, re-read rows and shared 128-byte lines hit in L2).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ void xcd_split(int nslow, int nfast, int& slow, int& fast) {
+  const int total = nslow * nfast;
+  const int b = blockIdx.y * gridDim.x + blockIdx.x;
+  const int q = total / NUM_XCD, r = total % NUM_XCD;
+  const int xcd = b % NUM_XCD;
+  const int logical = xcd * q + min(xcd, r) + b / NUM_XCD;
+  fast = logical % nfast;
+  slow = logical / nfast;
+}
 
 // periodic bilinear interpolation of the interleaved physical fields at x + xi
 template <typename T, int N>
@@ -161,52 +184,39 @@ __device__ __forceinline__ P4<T> gather4(const P4<T>* __restrict__ F, int x, int
 // --------------------------------------------------------------------------
 template <typename T, int N>
 __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d) {
-  constexpr int E = Plan<N>::E, NT = N / E, PW = 64 / NT, L = padded_len(N);
-  __shared__ cplx<T> lds[ROW_WAVES * PW * L];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / NT, t = lane % NT;
-  const int y = (blockIdx.x * ROW_WAVES + wave) * PW + grp;
-  if (y >= N) return;  // whole wavefronts only (N is a multiple of PW)
-  cplx<T>* buf = lds + (wave * PW + grp) * L;
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT;
+  __shared__ cplx<T> lds[G::RPB * G::L];
+  const int grp = row_group<NT>(), t = threadIdx.x % NT;
+  int rowblock, unused;
+  xcd_split(gridDim.x * gridDim.y, 1, rowblock, unused);
+  const int y = rowblock * G::RPB + grp;  // the grid covers the rows exactly
+  cplx<T>* buf = lds + grp * G::L;
   const size_t rf = d.rowfield_elems();
   const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
-  const int K = d.K;
+  constexpr int K = kcut<N>();
 
   cplx<T> uv[E], hz[E];
-  load_pair<T, N, false, false>(uv, ICr + IC_U * rf, ICr + IC_V * rf, t, K);
+  load_pair<T, N, false, false>(uv, ICr + IC_U * rf, ICr + IC_V * rf, t);
   inverse_row<T, N>(uv, buf, t, P.tw);
   // (eta + i zeta): zeta spectrum = i kx C_v - C_uy
   {
     const cplx<T>* Ch = ICr + IC_H * rf;
     const cplx<T>* Cv = ICr + IC_V * rf;
     const cplx<T>* Cuy = ICr + IC_UY * rf;
+    sched_fence();
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int k = t + NT * r;
-      int kk;
-      bool mirror;
-      if (k <= K) {
-        kk = k;
-        mirror = false;
-      } else if (k >= N - K) {
-        kk = N - k;
-        mirror = true;
-      } else {
-        hz[r] = {T(0), T(0)};
-        continue;
-      }
+      const bool lo = k <= K, hi = k >= N - K;
+      const int kk = min(lo ? k : N - k, K);
       cplx<T> a = Ch[kk];
       const cplx<T> cv = Cv[kk], cu = Cuy[kk];
       cplx<T> b = {-T(kk) * cv.y - cu.x, T(kk) * cv.x - cu.y};
-      if (kk == 0) {
-        a.y = T(0);
-        b.y = T(0);
-      }
-      if (mirror) {
-        a.y = -a.y;
-        b.y = -b.y;
-      }
-      hz[r] = {a.x - b.y, a.y + b.x};
+      const T sy = (kk == 0) ? T(0) : (hi ? T(-1) : T(1));
+      a.y *= sy;
+      b.y *= sy;
+      hz[r] = (lo || hi) ? cplx<T>{a.x - b.y, a.y + b.x} : cplx<T>{T(0), T(0)};
     }
   }
   inverse_row<T, N>(hz, buf, t, P.tw);
@@ -219,40 +229,47 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims
   cplx<T> z[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
-  forward_row<T, N, true>(z, buf, t, P.tw, K, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
+  forward_row<T, N, true>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
 #pragma unroll
   for (int e = 0; e < E; ++e)
     z[e] = {T(0.5) * (uv[e].x * uv[e].x + uv[e].y * uv[e].y), hz[e].x * uv[e].x};  // K, eta u
-  forward_row<T, N, true>(z, buf, t, P.tw, K, RSr + RS_K * rf, RSr + RS_HU * rf);
+  forward_row<T, N, true>(z, buf, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = {hz[e].x * uv[e].y, T(0)};  // eta v
-  forward_row<T, N, false>(z, buf, t, P.tw, K, RSr + RS_HV * rf, nullptr);
+  forward_row<T, N, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
 }
 
 // --------------------------------------------------------------------------
 // rows_rhs
 // --------------------------------------------------------------------------
+// tasks (one wavefront per row and task; four light tasks keep the register
+// footprint, hence occupancy, reasonable):
+//   RT_XI  strategy 2, both xi components (eq. (4.5a))
+//   RT_GB  strategy 2, g-bar of eta and zeta (eq. (4.5b))
+//   RT_GT  strategy 1, g-tilde of eta and zeta (eq. (4.1))
+//   RT_P   strategy 1, both P components (eq. (3.9) in P form)
+// The two strategy-2 tasks each transform xi and gather at x + xi.
 template <typename T, int N>
 __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s) {
-  constexpr int E = Plan<N>::E, NT = N / E, PW = 64 / NT, L = padded_len(N);
-  __shared__ cplx<T> lds[ROW_WAVES * PW * L];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / NT, t = lane % NT;
-  const int y = (blockIdx.x * ROW_WAVES + wave) * PW + grp;
-  if (y >= N) return;
-  cplx<T>* buf = lds + (wave * PW + grp) * L;
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT;
+  __shared__ cplx<T> lds[G::RPB * G::L];
+  const int grp = row_group<NT>(), t = threadIdx.x % NT;
+  int rowblock, task;
+  xcd_split(gridDim.x, gridDim.y, rowblock, task);  // grid = (row blocks, tasks)
+  const int y = rowblock * G::RPB + grp;  // the grid covers the rows exactly
+  cplx<T>* buf = lds + grp * G::L;
   const size_t rf = d.rowfield_elems();
   const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
   cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
   const P4<T>* F = P.uvhz;
   const P4<T>* Fr = P.uvhz + (size_t)y * N;
-  const int K = d.K;
-  const int task = blockIdx.y;
+  constexpr int K = kcut<N>();
 
-  cplx<T> a[E], b[E], c[E];
-  if (task == RT_XI || task == RT_GBAR) {
-    // displacement and the partial-mean velocity w
-    load_pair<T, N, false, false>(a, ICr + IC_XIX * rf, ICr + IC_XIY * rf, t, K);
+  cplx<T> a[E], b[E];
+  if (task == RT_XI || task == RT_GB) {
+    // displacement xi, partial-mean velocity w = xi / (t - tau) (u/2 at t = tau)
+    load_pair<T, N, false, false>(a, ICr + IC_XIX * rf, ICr + IC_XIY * rf, t);
     inverse_row<T, N>(a, buf, t, P.tw);
     cplx<T> w[E];
     if (s > 0.0) {
@@ -266,52 +283,59 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims
         w[e] = {T(0.5) * q.u, T(0.5) * q.v};
       }
     }
-    if (task == RT_XI) {
-      load_pair<T, N, true, false>(b, ICr + IC_XIX * rf, ICr + IC_XIX_Y * rf, t, K);
-      inverse_row<T, N>(b, buf, t, P.tw);  // (d xi_x/dx, d xi_x/dy)
-      load_pair<T, N, true, false>(c, ICr + IC_XIY * rf, ICr + IC_XIY_Y * rf, t, K);
-      inverse_row<T, N>(c, buf, t, P.tw);  // (d xi_y/dx, d xi_y/dy)
+    sched_fence();
+    // gathered terms at x + xi, in groups of GG points (bounds loads in flight)
+    constexpr int GG = 4;
+    static_assert(E % GG == 0, "gather groups");
+    const bool xi_task = (task == RT_XI);
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const P4<T> g = gather4<T, N>(F, t + NT * e, y, a[e].x, a[e].y);
-        const T rx = g.u - w[e].x - (w[e].x * b[e].x + w[e].y * b[e].y);
-        const T ry = g.v - w[e].y - (w[e].x * c[e].x + w[e].y * c[e].y);
-        a[e] = {rx, ry};
-      }
-      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_XIX * rf, RSr + RS_XIY * rf);
-    } else {
-      load_pair<T, N, true, false>(b, ICr + IC_GBH * rf, ICr + IC_GBH_Y * rf, t, K);
-      inverse_row<T, N>(b, buf, t, P.tw);
-      load_pair<T, N, true, false>(c, ICr + IC_GBZ * rf, ICr + IC_GBZ_Y * rf, t, K);
-      inverse_row<T, N>(c, buf, t, P.tw);
+    for (int e0 = 0; e0 < E; e0 += GG) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
+      for (int e = e0; e < e0 + GG; ++e) {
         const P4<T> g = gather4<T, N>(F, t + NT * e, y, a[e].x, a[e].y);
-        const T rh = g.h - (w[e].x * b[e].x + w[e].y * b[e].y);
-        const T rz = g.z - (w[e].x * c[e].x + w[e].y * c[e].y);
-        a[e] = {rh, rz};
+        a[e] = xi_task ? cplx<T>{g.u - w[e].x, g.v - w[e].y} : cplx<T>{g.h, g.z};
       }
-      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_GBH * rf, RSr + RS_GBZ * rf);
+      sched_fence();
     }
-  } else {
-    const int i1 = (task == RT_GTIL) ? IC_GTH : IC_PX;
-    const int i2 = (task == RT_GTIL) ? IC_GTZ : IC_PY;
-    load_pair<T, N, true, false>(b, ICr + i1 * rf, ICr + (i1 + 1) * rf, t, K);
+    // minus w . grad of (xi_x, xi_y) or of (g-bar_h, g-bar_zeta)
+    const int f1 = xi_task ? IC_XIX : IC_GBH, f2 = xi_task ? IC_XIY : IC_GBZ;
+    load_pair<T, N, true, false>(b, ICr + f1 * rf, ICr + (f1 + 1) * rf, t);
     inverse_row<T, N>(b, buf, t, P.tw);
-    load_pair<T, N, true, false>(c, ICr + i2 * rf, ICr + (i2 + 1) * rf, t, K);
-    inverse_row<T, N>(c, buf, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e].x = a[e].x - (w[e].x * b[e].x + w[e].y * b[e].y);
+    load_pair<T, N, true, false>(b, ICr + f2 * rf, ICr + (f2 + 1) * rf, t);
+    inverse_row<T, N>(b, buf, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e].y = a[e].y - (w[e].x * b[e].x + w[e].y * b[e].y);
+    const int o = xi_task ? RS_XIX : RS_GBH;
+    forward_row<T, N, true>(a, buf, t, P.tw, RSr + o * rf, RSr + (o + 1) * rf);
+  } else {
+    // f - u . grad g-tilde (f = eta, zeta), or (t - tau) u - u . grad P
+    const bool gt = (task == RT_GT);
     const T sT = T(s);
+    cplx<T> uv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const P4<T> q = Fr[t + NT * e];
-      const T f1 = (task == RT_GTIL) ? q.h : sT * q.u;
-      const T f2 = (task == RT_GTIL) ? q.z : sT * q.v;
-      a[e] = {f1 - (q.u * b[e].x + q.v * b[e].y), f2 - (q.u * c[e].x + q.v * c[e].y)};
+      uv[e] = {q.u, q.v};
     }
-    if (task == RT_GTIL)
-      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_GTH * rf, RSr + RS_GTZ * rf);
-    else
-      forward_row<T, N, true>(a, buf, t, P.tw, K, RSr + RS_PX * rf, RSr + RS_PY * rf);
+    const int f1 = gt ? IC_GTH : IC_PX, f2 = gt ? IC_GTZ : IC_PY;
+    load_pair<T, N, true, false>(b, ICr + f1 * rf, ICr + (f1 + 1) * rf, t);
+    inverse_row<T, N>(b, buf, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T src = gt ? Fr[t + NT * e].h : sT * uv[e].x;
+      a[e].x = src - (uv[e].x * b[e].x + uv[e].y * b[e].y);
+    }
+    load_pair<T, N, true, false>(b, ICr + f2 * rf, ICr + (f2 + 1) * rf, t);
+    inverse_row<T, N>(b, buf, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T src = gt ? Fr[t + NT * e].z : sT * uv[e].y;
+      a[e].y = src - (uv[e].x * b[e].x + uv[e].y * b[e].y);
+    }
+    const int o = gt ? RS_GTH : RS_PX;
+    forward_row<T, N, true>(a, buf, t, P.tw, RSr + o * rf, RSr + (o + 1) * rf);
   }
 }
 
@@ -347,7 +371,7 @@ __device__ __forceinline__ cplx<TS> rk4(int stage, cplx<TS>* __restrict__ Yp, cp
 
 template <typename T, int N, int C>
 struct ColCtx {
-  static constexpr int E = Plan<N>::E, NT = N / E, LC = col_buf(N);
+  static constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
   cplx<T>* lds;     // C buffers of LC
   cplx<T>* buf;     // this group's buffer
   int c, t, kx0, kx;
@@ -364,7 +388,7 @@ __device__ __forceinline__ void tile_load(const ColCtx<T, N, C>& cx, const cplx<
     const int c = i % C, y = i / C;
     const int kx = cx.kx0 + c;
     cplx<T> val = {T(0), T(0)};
-    if (kx <= d.K) val = src[(size_t)y * d.NKXP + kx];
+    if (kx <= kcut<N>()) val = src[(size_t)y * d.NKXP + kx];
     cx.lds[c * LC + pidx(y)] = val;
   }
   __syncthreads();
@@ -378,7 +402,7 @@ __device__ __forceinline__ void tile_store(const ColCtx<T, N, C>& cx, cplx<T>* _
   for (int i = threadIdx.x; i < N * C; i += blockDim.x) {
     const int c = i % C, y = i / C;
     const int kx = cx.kx0 + c;
-    if (kx <= d.K) dst[(size_t)y * d.NKXP + kx] = cx.lds[c * LC + pidx(y)];
+    if (kx <= kcut<N>()) dst[(size_t)y * d.NKXP + kx] = cx.lds[c * LC + pidx(y)];
   }
   __syncthreads();
 }
@@ -387,14 +411,14 @@ __device__ __forceinline__ void tile_store(const ColCtx<T, N, C>& cx, cplx<T>* _
 // 1/N^2-normalised right-hand-side values at k = t + NT r
 template <typename T, int N, int C>
 __device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const cplx<T>* src, const Dims& d,
-                                               const cplx<T>* __restrict__ tw, cplx<T> (&out)[Plan<N>::E]) {
-  constexpr int E = Plan<N>::E, NT = N / E;
+                                               const cplx<T>* __restrict__ tw, cplx<T> (&out)[COL_E]) {
+  constexpr int E = COL_E, NT = N / E;
   tile_load<T, N, C>(cx, src, d);
   cplx<T> v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = cx.buf[pidx(cx.t + NT * r)];
-  wave_sync();
-  fft<T, N, -1>(v, cx.buf, cx.t, tw);
+  xsync<NT>();
+  fft<T, N, COL_E, -1>(v, cx.buf, cx.t, tw);
   const T inv = T(1.0 / (double(N) * double(N)));
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -406,9 +430,9 @@ __device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const 
 // inverse column transform of values S at k = t + NT r (already zero outside
 // the mask), optionally times i ky, stored to an intermediate field
 template <typename T, int N, int C, typename TS, bool DY>
-__device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const cplx<TS> (&S)[Plan<N>::E],
+__device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const cplx<TS> (&S)[COL_E],
                                                cplx<T>* dst, const Dims& d, const cplx<T>* __restrict__ tw) {
-  constexpr int E = Plan<N>::E, NT = N / E;
+  constexpr int E = COL_E, NT = N / E;
   cplx<T> v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -419,7 +443,7 @@ __device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const 
     v[r] = q;
   }
   __syncthreads();  // the tile buffers may still be read by the previous store
-  fft<T, N, +1>(v, cx.buf, cx.t, tw);
+  fft<T, N, COL_E, +1>(v, cx.buf, cx.t, tw);
   tile_store<T, N, C>(cx, dst, d);
 }
 
@@ -427,12 +451,12 @@ template <typename T, int N, int C, int G>
 __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const StepPtrs<T>& P, const Dims& d,
                                              const Phys& ph, int stage, const cplx<T>* __restrict__ Ys_in,
                                              cplx<T>* __restrict__ Ys_out) {
-  constexpr int E = Plan<N>::E, NT = N / E;
+  constexpr int E = COL_E, NT = N / E;
   constexpr bool DBL = (G == CG_XIX || G == CG_XIY || G == CG_PX || G == CG_PY);
   using TS = typename std::conditional<DBL, double, T>::type;
   const size_t sp = d.spec_elems();
   const size_t rf = d.rowfield_elems();
-  const int K = d.K;
+  constexpr int K = kcut<N>();
 
   // right-hand-side inputs of this group
   constexpr int NF = (G == CG_U || G == CG_V || G == CG_H) ? 2 : 1;
@@ -541,17 +565,19 @@ template <typename T, int N>
 __global__ void __launch_bounds__(col_tile(N) * (N / 16))
     k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out) {
   constexpr int C = col_tile(N);
-  constexpr int E = Plan<N>::E, NT = N / E, LC = col_buf(N);
+  constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
   __shared__ cplx<T> lds[C * LC];
   ColCtx<T, N, C> cx;
   cx.lds = lds;
   cx.c = threadIdx.x / NT;
   cx.t = threadIdx.x % NT;
   cx.buf = lds + cx.c * LC;
-  cx.kx0 = blockIdx.x * C;
+  int tile, group;
+  xcd_split(gridDim.x, gridDim.y, tile, group);  // grid = (column tiles, field groups)
+  cx.kx0 = tile * C;
   cx.kx = cx.kx0 + cx.c;
-  cx.valid = cx.kx <= d.K;
-  switch (blockIdx.y) {
+  cx.valid = cx.kx <= kcut<N>();
+  switch (group) {
     case CG_U: column_group<T, N, C, CG_U>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
     case CG_V: column_group<T, N, C, CG_V>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
     case CG_H: column_group<T, N, C, CG_H>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
