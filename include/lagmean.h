@@ -117,11 +117,12 @@ lm_status lm_begin_interval(lm_run* run);
    LM_E_STATE before lm_set_state. */
 lm_status lm_step(lm_run* run, int32_t nsteps);
 
-/* As lm_step, but every kernel launch is bracketed by HIP events on the run's
-   stream and the stream is synchronised after each RK4 stage.  ms_avg[0..2]
-   receive the average duration in milliseconds of the three hot-path kernels:
-   [0] rows pass of the dynamics, [1] rows pass of the mean right-hand sides,
-   [2] column pass (spectral assembly + RK4).  nsteps > 0.  For measurement. */
+/* As lm_step, but every kernel launch is bracketed by a pair of HIP events on
+   the run's stream (all enqueued back to back; one synchronisation at the end).
+   ms_avg[0..2] receive the average duration in milliseconds of the three
+   hot-path kernels: [0] rows pass of the dynamics, [1] rows pass of the mean
+   right-hand sides, [2] column pass (spectral assembly + RK4).
+   1 <= nsteps <= 4096.  Synchronous.  For measurement. */
 lm_status lm_step_profiled(lm_run* run, int32_t nsteps, double* ms_avg);
 
 /* Close the interval: T = (steps since begin) * dt; computes the outputs

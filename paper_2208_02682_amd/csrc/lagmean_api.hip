@@ -256,7 +256,7 @@ lm_status lm_step(lm_run* r, int32_t nsteps) {
 
 lm_status lm_step_profiled(lm_run* r, int32_t nsteps, double* ms_avg) {
   if (!r || !ms_avg) return fail(LM_E_ARG, "null argument");
-  if (nsteps <= 0) return fail(LM_E_ARG, "nsteps must be positive");
+  if (nsteps <= 0 || nsteps > 4096) return fail(LM_E_ARG, "nsteps must be in 1..4096");
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
   double ms[3] = {0.0, 0.0, 0.0};
   hipError_t e = hipSuccess;

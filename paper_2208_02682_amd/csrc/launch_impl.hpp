@@ -2,12 +2,17 @@
 #pragma once
 
 #include <type_traits>
+#include <vector>
 
 #include "io_kernels.hpp"
 #include "launch.hpp"
 #include "step_kernels.hpp"
 
 namespace lm {
+
+// does nothing; used to separate timed launches
+template <int N>
+__global__ void k_drain() {}
 
 template <typename T>
 StepPtrs<T> step_ptrs(RunView& r) {
@@ -64,43 +69,53 @@ void launch_steps_t(RunView& r, int nsteps) {
   }
 }
 
-// Same launches as launch_steps_t, each bracketed by events on the run's
-// stream; the stream is synchronised after every stage and the three kernel
-// durations are accumulated into ms[0..2].
+// Same launches as launch_steps_t, each bracketed by a pair of events on the
+// run's stream; nothing synchronises until all steps are enqueued, so the
+// kernels run back to back as in launch_steps_t.  The three kernel durations
+// are accumulated into ms[0..2].
 template <typename T, int N>
 hipError_t launch_steps_profiled_t(RunView& r, int nsteps, double* ms) {
   const StepPtrs<T> P = step_ptrs<T>(r);
   static const double c[4] = {0.0, 0.5, 0.5, 1.0};
-  hipEvent_t ev[6];
-  for (auto& e : ev) {
-    hipError_t err = hipEventCreate(&e);
-    if (err != hipSuccess) return err;
-  }
+  const int nev = nsteps * 4 * 3 * 2;
+  std::vector<hipEvent_t> ev(nev);
   hipError_t err = hipSuccess;
-  for (int s = 0; s < nsteps && err == hipSuccess; ++s) {
+  int made = 0;
+  // device-scope markers: no system-scope cache release around every launch
+  for (; made < nev && err == hipSuccess; ++made) err = hipEventCreateWithFlags(&ev[made], hipEventDisableSystemFence);
+  if (err != hipSuccess) {
+    for (int i = 0; i < made - 1; ++i) (void)hipEventDestroy(ev[i]);
+    return err;
+  }
+  int e = 0;
+  for (int s = 0; s < nsteps; ++s) {
     for (int stage = 0; stage < 4; ++stage) {
       const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
-      (void)hipEventRecord(ev[0], r.stream);
+      // an empty kernel between one kernel's end marker and the next one's
+      // start marker absorbs the work done at kernel boundaries, so each
+      // interval covers one kernel's execution only
+      (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d);
-      (void)hipEventRecord(ev[1], r.stream);
+      (void)hipEventRecord(ev[e++], r.stream);
+      hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
+      (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL((k_rows_rhs<T, N>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
-      (void)hipEventRecord(ev[2], r.stream);
-      (void)hipEventRecord(ev[3], r.stream);
+      (void)hipEventRecord(ev[e++], r.stream);
+      hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
+      (void)hipEventRecord(ev[e++], r.stream);
       launch_columns_t<T, N>(r, stage);
-      (void)hipEventRecord(ev[4], r.stream);
-      err = hipEventSynchronize(ev[4]);
-      if (err != hipSuccess) break;
-      float a = 0.f, b = 0.f, cc = 0.f;
-      (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-      (void)hipEventElapsedTime(&b, ev[1], ev[2]);
-      (void)hipEventElapsedTime(&cc, ev[3], ev[4]);
-      ms[0] += a;
-      ms[1] += b;
-      ms[2] += cc;
+      (void)hipEventRecord(ev[e++], r.stream);
+      hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
     }
     r.n += 1;
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
+  err = hipEventSynchronize(ev[nev - 1]);
+  for (int i = 0; i < nev && err == hipSuccess; i += 2) {
+    float t = 0.f;
+    err = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+    ms[(i / 2) % 3] += t;
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
   return err;
 }
 
