@@ -74,7 +74,7 @@ typedef enum { LM_FP64 = 0, LM_FP32_MIXED = 1 } lm_precision;
 #define LM_DYNAMIC 0
 
 typedef struct {
-  int32_t n;           /* grid points per side: 64, 128, 256, 512 or 1024 */
+  int32_t n;           /* grid points per side: 64, 128, 192, 256, 384, 512 or 1024 */
   int32_t precision;   /* LM_FP64: everything float64.  LM_FP32_MIXED: transforms,
                           products and gathers in float32; the xi and P state, their
                           RK4 accumulators and the end-of-interval outputs (division

@@ -150,6 +150,53 @@ __device__ __forceinline__ void dft16(cplx<T>* v) {
   }
 }
 
+template <int DIR, typename T>
+__device__ __forceinline__ void dft3(cplx<T>& a, cplx<T>& b, cplx<T>& c) {
+  constexpr T h = T(0.86602540378443864676372317075293618347);  // sqrt(3)/2
+  const cplx<T> t1 = b + c;
+  const cplx<T> t2 = {a.x - T(0.5) * t1.x, a.y - T(0.5) * t1.y};
+  const cplx<T> d = b - c;
+  // t3 = DIR i (sqrt 3 / 2) (b - c)
+  const cplx<T> t3 = (DIR < 0) ? cplx<T>{h * d.y, -h * d.x} : cplx<T>{-h * d.y, h * d.x};
+  a = a + t1;
+  b = t2 + t3;
+  c = t2 - t3;
+}
+
+// 12 = 3 x 4: inner radix-3 DFTs over r1 (r = 4 r1 + r2), twiddles w12^{r2 q1},
+// outer radix-4 DFTs over r2, output index q = q1 + 3 q2
+template <int DIR, typename T>
+__device__ __forceinline__ void dft12(cplx<T>* v) {
+  constexpr T c6 = T(0.86602540378443864676372317075293618347);  // cos(pi/6)
+  cplx<T> X[12];
+#pragma unroll
+  for (int r2 = 0; r2 < 4; ++r2) {
+    cplx<T> a = v[r2], b = v[4 + r2], c = v[8 + r2];
+    dft3<DIR>(a, b, c);
+    X[r2 * 3 + 0] = a;
+    X[r2 * 3 + 1] = b;
+    X[r2 * 3 + 2] = c;
+  }
+  const T sg = T(DIR);
+  const cplx<T> w1 = {c6, sg * T(0.5)}, w2 = {T(0.5), sg * c6}, w4 = {T(-0.5), sg * c6};
+  // r2 = 1: q1 = 1, 2 -> w1, w2; r2 = 2: w2, w4; r2 = 3: w3 = DIR i, w6 = -1
+  X[4] = cmul(X[4], w1);
+  X[5] = cmul(X[5], w2);
+  X[7] = cmul(X[7], w2);
+  X[8] = cmul(X[8], w4);
+  X[10] = rot90<DIR>(X[10]);
+  X[11] = {-X[11].x, -X[11].y};
+#pragma unroll
+  for (int q1 = 0; q1 < 3; ++q1) {
+    cplx<T> a = X[q1], b = X[3 + q1], c = X[6 + q1], d = X[9 + q1];
+    dft4<DIR>(a, b, c, d);
+    v[q1] = a;
+    v[q1 + 3] = b;
+    v[q1 + 6] = c;
+    v[q1 + 9] = d;
+  }
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cplx<T>* v) {
   if constexpr (R == 2) {
@@ -160,8 +207,12 @@ __device__ __forceinline__ void dft(cplx<T>* v) {
     dft8<DIR>(v);
   } else if constexpr (R == 16) {
     dft16<DIR>(v);
+  } else if constexpr (R == 3) {
+    dft3<DIR>(v[0], v[1], v[2]);
+  } else if constexpr (R == 12) {
+    dft12<DIR>(v);
   } else {
-    static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+    static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 12 || R == 16, "unsupported radix");
   }
 }
 
@@ -183,13 +234,16 @@ template <> struct Plan<128, 8>   { static constexpr int R2 = 8,  R3 = 2, R4 = 1
 template <> struct Plan<256, 8>   { static constexpr int R2 = 8,  R3 = 4, R4 = 1; };
 template <> struct Plan<512, 8>   { static constexpr int R2 = 8,  R3 = 8, R4 = 1; };
 template <> struct Plan<1024, 8>  { static constexpr int R2 = 8,  R3 = 8, R4 = 2; };
+template <> struct Plan<192, 12>  { static constexpr int R2 = 4,  R3 = 4, R4 = 1; };
+template <> struct Plan<384, 12>  { static constexpr int R2 = 4,  R3 = 4, R4 = 2; };
 
-// values per lane of the column and row passes.  16 keeps a 1024-point
-// transform inside one wavefront (no workgroup barriers); measured on the
-// 1024^2 workload it beats 8 values per lane (which halves the registers but
-// needs a barrier per exchange) by about 25% in the row passes.
-constexpr int COL_E = 16;
-constexpr int ROW_E = 16;
+// values per lane of the column and row passes: 16 for powers of two (a
+// 1024-point transform stays inside one wavefront, no workgroup barriers;
+// measured on the 1024^2 workload it beats 8 values per lane, which halves the
+// registers but needs a barrier per exchange, by about 25% in the row passes),
+// 12 for N = 3 * 2^k (first stage radix 12 = 3 x 4)
+template <int N>
+__host__ __device__ constexpr int fft_E() { return (N % 3 == 0) ? 12 : 16; }
 
 // exchanges of a transform owned by NT lanes: wavefront-scope ordering when the
 // transform lives in one wavefront, a workgroup barrier otherwise

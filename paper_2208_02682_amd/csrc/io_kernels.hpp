@@ -55,10 +55,10 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_io_row_inverse(IoRowInv J, D
 }
 
 template <int N>
-__global__ void __launch_bounds__(col_tile(N) * (N / 16))
+__global__ void __launch_bounds__(col_threads<N>())
     k_io_col_forward(IoColFwd J, Dims d, const cplx<double>* tw) {
-  constexpr int C = col_tile(N);
-  constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
+  constexpr int C = col_tile<N>();
+  constexpr int E = fft_E<N>(), NT = N / E, LC = col_buf(N);
   __shared__ cplx<double> lds[C * LC];
   ColCtx<double, N, C> cx;
   cx.lds = lds;
@@ -89,10 +89,10 @@ __global__ void __launch_bounds__(col_tile(N) * (N / 16))
 }
 
 template <int N>
-__global__ void __launch_bounds__(col_tile(N) * (N / 16))
+__global__ void __launch_bounds__(col_threads<N>())
     k_io_col_inverse(IoColInv J, Dims d, const cplx<double>* tw) {
-  constexpr int C = col_tile(N);
-  constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
+  constexpr int C = col_tile<N>();
+  constexpr int E = fft_E<N>(), NT = N / E, LC = col_buf(N);
   __shared__ cplx<double> lds[C * LC];
   ColCtx<double, N, C> cx;
   cx.lds = lds;

@@ -32,11 +32,13 @@ lm_status fail(lm_status s, const std::string& msg) {
     if (e_ != hipSuccess) return fail(LM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-bool supported_n(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+bool supported_n(int n) {
+  return n == 64 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512 || n == 1024;
+}
 
 lm_status check_cfg(const lm_config* cfg) {
   if (!cfg) return fail(LM_E_ARG, "null config");
-  if (!supported_n(cfg->n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 256, 512 or 1024");
+  if (!supported_n(cfg->n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 192, 256, 384, 512 or 1024");
   if (cfg->precision != LM_FP64 && cfg->precision != LM_FP32_MIXED)
     return fail(LM_E_ARG, "precision must be LM_FP64 or LM_FP32_MIXED");
   if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return fail(LM_E_ARG, "dt must be positive and finite");

@@ -20,7 +20,9 @@ void launch_nonfinite(RunView& r, const double* a, size_t n, int* flag);
   switch (n) {                                    \
     case 64: out = FN<64>(__VA_ARGS__); break;    \
     case 128: out = FN<128>(__VA_ARGS__); break;  \
+    case 192: out = FN<192>(__VA_ARGS__); break;  \
     case 256: out = FN<256>(__VA_ARGS__); break;  \
+    case 384: out = FN<384>(__VA_ARGS__); break;  \
     case 512: out = FN<512>(__VA_ARGS__); break;  \
     case 1024: out = FN<1024>(__VA_ARGS__); break;\
     default: break;                               \
@@ -30,7 +32,9 @@ void launch_nonfinite(RunView& r, const double* a, size_t n, int* flag);
   switch (n) {                               \
     case 64: FN<64>(__VA_ARGS__); break;     \
     case 128: FN<128>(__VA_ARGS__); break;   \
+    case 192: FN<192>(__VA_ARGS__); break;   \
     case 256: FN<256>(__VA_ARGS__); break;   \
+    case 384: FN<384>(__VA_ARGS__); break;   \
     case 512: FN<512>(__VA_ARGS__); break;   \
     case 1024: FN<1024>(__VA_ARGS__); break; \
     default: break;                          \

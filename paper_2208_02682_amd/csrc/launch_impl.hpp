@@ -34,12 +34,12 @@ dim3 row_grid(int tasks) {
 }
 template <int N>
 dim3 col_grid(const Dims& d, int groups) {
-  constexpr int C = col_tile(N);
+  constexpr int C = col_tile<N>();
   return dim3((d.NKX + C - 1) / C, groups);
 }
 template <int N>
 dim3 col_block() {
-  return dim3(col_tile(N) * (N / 16));
+  return dim3(col_threads<N>());
 }
 
 template <typename T, int N>

@@ -56,10 +56,10 @@ struct StepPtrs {
 
 constexpr int ROW_WAVES = 4;  // wavefronts per row-kernel block
 
-// row kernels: one lane group of NT = N / ROW_E lanes per grid row
+// row kernels: one lane group of NT = N / E lanes per grid row
 template <int N>
 struct RowGeo {
-  static constexpr int E = ROW_E, NT = N / E;
+  static constexpr int E = fft_E<N>(), NT = N / E;
   static constexpr int RPB = 64 * ROW_WAVES / NT;  // rows per block
   static constexpr int L = padded_len(N);           // LDS slots per row
   static_assert(RPB >= 1 && N % RPB == 0, "row geometry");
@@ -72,9 +72,14 @@ __device__ __forceinline__ int row_group() {
   else return threadIdx.x / NT;
 }
 
-__host__ __device__ constexpr int col_tile(int N) {
-  return (N / 16 >= 8) ? 8 : 64 / (N / 16);
+// column tile width: 8 columns (64-byte row segments in float32), or more when a
+// transform needs fewer than 8 lanes, so that a block is at least one wavefront
+template <int N>
+__host__ __device__ constexpr int col_tile() {
+  return (N / fft_E<N>() >= 8) ? 8 : 64 / (N / fft_E<N>());
 }
+template <int N>
+__host__ __device__ constexpr int col_threads() { return col_tile<N>() * (N / fft_E<N>()); }
 __host__ __device__ constexpr int col_buf(int N) { return padded_len(N) | 1; }
 
 // --------------------------------------------------------------------------
@@ -85,9 +90,9 @@ __host__ __device__ constexpr int col_buf(int N) { return padded_len(N) | 1; }
 // from their half spectra A, B (kx = 0..K).  A' = i kx A if DXA (likewise B).
 // Index k = t + NT r; negative kx are the conjugate mirror.
 template <typename T, int N, bool DXA, bool DXB>
-__device__ __forceinline__ void load_pair(cplx<T> (&z)[ROW_E], const cplx<T>* __restrict__ A,
+__device__ __forceinline__ void load_pair(cplx<T> (&z)[fft_E<N>()], const cplx<T>* __restrict__ A,
                                           const cplx<T>* __restrict__ B, int t) {
-  constexpr int E = ROW_E, NT = N / E, K = kcut<N>();
+  constexpr int E = fft_E<N>(), NT = N / E, K = kcut<N>();
   sched_fence();
   // branch-free: every lane loads (a clamped index where the mask is empty) and
   // selects, so the unrolled loop has no lane-divergent control flow
@@ -108,9 +113,9 @@ __device__ __forceinline__ void load_pair(cplx<T> (&z)[ROW_E], const cplx<T>* __
 
 // Inverse-transform a pair and leave lane values p[e] at x = t + NT e.
 template <typename T, int N>
-__device__ __forceinline__ void inverse_row(cplx<T> (&z)[ROW_E], cplx<T>* buf, int t,
+__device__ __forceinline__ void inverse_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* buf, int t,
                                             const cplx<T>* __restrict__ tw) {
-  constexpr int E = ROW_E, NT = N / E;
+  constexpr int E = fft_E<N>(), NT = N / E;
   fft<T, N, E, +1>(z, buf, t, tw);
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = buf[pidx(t + NT * e)];
@@ -121,10 +126,10 @@ __device__ __forceinline__ void inverse_row(cplx<T> (&z)[ROW_E], cplx<T>* buf, i
 // Forward-transform z = a + i b (lane values at x = t + NT e) and store the
 // half spectra of a and b (kx = 0..K) to the row pointers OA and OB.
 template <typename T, int N, bool TWO>
-__device__ __forceinline__ void forward_row(cplx<T> (&z)[ROW_E], cplx<T>* buf, int t,
+__device__ __forceinline__ void forward_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* buf, int t,
                                             const cplx<T>* __restrict__ tw,
                                             cplx<T>* __restrict__ OA, cplx<T>* __restrict__ OB) {
-  constexpr int E = ROW_E, NT = N / E, K = kcut<N>();
+  constexpr int E = fft_E<N>(), NT = N / E, K = kcut<N>();
   fft<T, N, E, -1>(z, buf, t, tw);
   for (int k = t; k <= K; k += NT) {
     const cplx<T> zk = buf[pidx(k)];
@@ -371,7 +376,7 @@ __device__ __forceinline__ cplx<TS> rk4(int stage, cplx<TS>* __restrict__ Yp, cp
 
 template <typename T, int N, int C>
 struct ColCtx {
-  static constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
+  static constexpr int E = fft_E<N>(), NT = N / E, LC = col_buf(N);
   cplx<T>* lds;     // C buffers of LC
   cplx<T>* buf;     // this group's buffer
   int c, t, kx0, kx;
@@ -411,14 +416,14 @@ __device__ __forceinline__ void tile_store(const ColCtx<T, N, C>& cx, cplx<T>* _
 // 1/N^2-normalised right-hand-side values at k = t + NT r
 template <typename T, int N, int C>
 __device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const cplx<T>* src, const Dims& d,
-                                               const cplx<T>* __restrict__ tw, cplx<T> (&out)[COL_E]) {
-  constexpr int E = COL_E, NT = N / E;
+                                               const cplx<T>* __restrict__ tw, cplx<T> (&out)[fft_E<N>()]) {
+  constexpr int E = fft_E<N>(), NT = N / E;
   tile_load<T, N, C>(cx, src, d);
   cplx<T> v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = cx.buf[pidx(cx.t + NT * r)];
   xsync<NT>();
-  fft<T, N, COL_E, -1>(v, cx.buf, cx.t, tw);
+  fft<T, N, fft_E<N>(), -1>(v, cx.buf, cx.t, tw);
   const T inv = T(1.0 / (double(N) * double(N)));
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -430,9 +435,9 @@ __device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const 
 // inverse column transform of values S at k = t + NT r (already zero outside
 // the mask), optionally times i ky, stored to an intermediate field
 template <typename T, int N, int C, typename TS, bool DY>
-__device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const cplx<TS> (&S)[COL_E],
+__device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const cplx<TS> (&S)[fft_E<N>()],
                                                cplx<T>* dst, const Dims& d, const cplx<T>* __restrict__ tw) {
-  constexpr int E = COL_E, NT = N / E;
+  constexpr int E = fft_E<N>(), NT = N / E;
   cplx<T> v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -443,7 +448,7 @@ __device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const 
     v[r] = q;
   }
   __syncthreads();  // the tile buffers may still be read by the previous store
-  fft<T, N, COL_E, +1>(v, cx.buf, cx.t, tw);
+  fft<T, N, fft_E<N>(), +1>(v, cx.buf, cx.t, tw);
   tile_store<T, N, C>(cx, dst, d);
 }
 
@@ -451,7 +456,7 @@ template <typename T, int N, int C, int G>
 __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const StepPtrs<T>& P, const Dims& d,
                                              const Phys& ph, int stage, const cplx<T>* __restrict__ Ys_in,
                                              cplx<T>* __restrict__ Ys_out) {
-  constexpr int E = COL_E, NT = N / E;
+  constexpr int E = fft_E<N>(), NT = N / E;
   constexpr bool DBL = (G == CG_XIX || G == CG_XIY || G == CG_PX || G == CG_PY);
   using TS = typename std::conditional<DBL, double, T>::type;
   const size_t sp = d.spec_elems();
@@ -562,10 +567,10 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
 
 // stage >= 0: RK4 stage; stage < 0: only transform the current state (prologue)
 template <typename T, int N>
-__global__ void __launch_bounds__(col_tile(N) * (N / 16))
+__global__ void __launch_bounds__(col_threads<N>())
     k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out) {
-  constexpr int C = col_tile(N);
-  constexpr int E = COL_E, NT = N / E, LC = col_buf(N);
+  constexpr int C = col_tile<N>();
+  constexpr int E = fft_E<N>(), NT = N / E, LC = col_buf(N);
   __shared__ cplx<T> lds[C * LC];
   ColCtx<T, N, C> cx;
   cx.lds = lds;

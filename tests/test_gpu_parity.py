@@ -39,7 +39,7 @@ def _band_limited(N, seed, K=None):
     return out
 
 
-@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("N", [64, 128, 192, 256, 384, 512, 1024])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_set_get_state_roundtrip(lib, N, prec):
     say(f"roundtrip N={N} {prec}")
@@ -139,6 +139,23 @@ def test_short_run_full_size_fp64(lib, name, steps):
         err = compare_value(k, got[0][k], ref[0][k])
         say(f"  {k}: rel {err:.3e}")
         assert err < TOL64, k
+    run.close()
+
+
+@pytest.mark.parametrize("N,prec", [(128, "fp64"), (192, "fp64"), (384, "fp64"), (192, "fp32"), (512, "fp32")])
+def test_short_run_every_grid_size(lib, N, prec):
+    """Every supported N (radix-2 and radix-3 transforms) against the oracle."""
+    from synth.workloads import scaled_run
+    w = scaled_run(N, Ro=0.08, ratio=1.5, periods=1.0, seeds=(31, 32), precision=prec)
+    steps = 9
+    say(f"N={N} {prec}: {steps} steps")
+    _, ref = oracle_run(w, steps_per_interval=steps, n_intervals=1)
+    run, got = gpu_run(w, steps_per_interval=steps, n_intervals=1)
+    tol = TOL64 if prec == "fp64" else TOL32
+    for k in OUTPUT_KEYS:
+        err = compare_value(k, got[0][k], ref[0][k])
+        say(f"  {k}: rel {err:.3e}")
+        assert err < tol, k
     run.close()
 
 
