@@ -164,8 +164,44 @@ lm_status lm_peek(lm_run* run, int32_t which, double* out, int on_device);
 /* Steps taken since lm_set_state and since lm_begin_interval. */
 lm_status lm_counters(lm_run* run, int64_t* steps, int64_t* steps_in_interval);
 
-/* Release every device buffer of the run (waits for its stream).  Null is a no-op. */
+/* Release every device buffer of the run (waits for its stream).  Null is a
+   no-op.  LM_E_STATE while the run belongs to a batch. */
 lm_status lm_destroy(lm_run* run);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent runs of any grid size and precision advanced
+ * together.  One RK4 step of all active members is one captured HIP graph: per
+ * (N, precision) group the three hot kernels are launched once for all the
+ * group's runs (blockIdx.z selects the run), groups are parallel branches of
+ * the graph.  Each member computes exactly what it computes alone (same
+ * kernels, same arithmetic, no cross-run reductions), bit for bit.
+ * A member must not be used through the single-run calls, or destroyed,
+ * while it belongs to a batch.
+ * ------------------------------------------------------------------------- */
+typedef struct lm_batch lm_batch;
+
+/* Empty batch.  Its graphs are captured and launched on a stream of its own;
+   lm_batch_step first waits for hip_stream (0 = the null stream). */
+lm_status lm_batch_create(void* hip_stream, lm_batch** out);
+
+/* Add a run that has a state and an open averaging interval, with a budget of
+   steps >= 0 RK4 steps.  Waits for the run's own stream.  LM_E_STATE if the run
+   has no open interval or already belongs to a batch. */
+lm_status lm_batch_add(lm_batch* b, lm_run* run, int32_t steps);
+
+/* Remove a member (its step counters stay as advanced). */
+lm_status lm_batch_remove(lm_batch* b, lm_run* run);
+
+/* Advance every member by min(max_steps, its remaining budget) RK4 steps.
+   Synchronous.  *active (may be null) receives the number of members with
+   budget left afterwards. */
+lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active);
+
+/* Remaining budget of a member. */
+lm_status lm_batch_remaining(lm_batch* b, const lm_run* run, int32_t* remaining);
+
+/* Release the batch (members are removed, not destroyed).  Null is a no-op. */
+lm_status lm_batch_destroy(lm_batch* b);
 
 /* Text of a status code (static storage). */
 const char* lm_status_str(lm_status s);

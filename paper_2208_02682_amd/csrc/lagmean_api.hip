@@ -10,6 +10,7 @@
 #include <string>
 #include <type_traits>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "lagmean.h"
@@ -60,6 +61,32 @@ struct lm_run : lm::RunView {
   lm_config cfg;
   bool has_state, in_interval, has_mean;
   double T;
+  lm_batch* batch;  // the batch this run belongs to, if any
+};
+
+struct lm_batch {
+  struct Member {
+    lm_run* run;
+    int32_t remaining;
+  };
+  struct Group {
+    int N;
+    bool fp32;
+    void* d_desc = nullptr;  // device array of RunDesc<T>
+    size_t cap = 0;          // bytes
+    hipStream_t fork = nullptr;
+    hipEvent_t join = nullptr;
+  };
+  hipStream_t user;     // the caller's stream (ordering only)
+  hipStream_t stream;   // the batch's own stream: graphs are captured and launched here
+  std::vector<Member> members;
+  std::vector<Group> groups;
+  long long* d_counters = nullptr;  // one per member slot
+  int counter_cap = 0;
+  hipEvent_t fork_ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<lm_run*> signature;  // active members the graph was built for
 };
 
 namespace {
@@ -146,6 +173,7 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
   r->T = 0.0;
   r->ys_cur = 0;
   r->slab = nullptr;
+  r->batch = nullptr;
   hipError_t e = hipMalloc((void**)&r->slab, r->L.total);
   if (e != hipSuccess) {
     delete r;
@@ -373,11 +401,239 @@ lm_status lm_counters(lm_run* r, int64_t* steps, int64_t* steps_in_interval) {
 
 lm_status lm_destroy(lm_run* r) {
   if (!r) return LM_OK;
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   hipError_t e = hipStreamSynchronize(r->stream);
   hipError_t e2 = hipFree(r->slab);
   delete r;
   if (e != hipSuccess) return fail(LM_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(LM_E_HIP, std::string("hipFree: ") + hipGetErrorString(e2));
+  return LM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+namespace {
+
+lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32) {
+  for (auto& g : b->groups)
+    if (g.N == N && g.fp32 == fp32) return &g;
+  lm_batch::Group g;
+  g.N = N;
+  g.fp32 = fp32;
+  if (hipStreamCreateWithFlags(&g.fork, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&g.join, hipEventDisableTiming) != hipSuccess) return nullptr;
+  b->groups.push_back(g);
+  return &b->groups.back();
+}
+
+template <typename T>
+std::vector<char> group_descs(lm_batch* b, int N, bool fp32, const std::vector<int>& active, int* count) {
+  std::vector<lm::RunDesc<T>> d;
+  for (int i : active) {
+    lm_run* r = b->members[i].run;
+    if (r->d.N == N && r->fp32 == fp32) d.push_back(lm::run_desc<T>(*r, b->d_counters + i));
+  }
+  *count = (int)d.size();
+  std::vector<char> bytes(d.size() * sizeof(lm::RunDesc<T>));
+  if (!d.empty()) memcpy(bytes.data(), d.data(), bytes.size());
+  return bytes;
+}
+
+void drop_graph(lm_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->signature.clear();
+}
+
+// descriptors of the active members, then one captured graph for one RK4 step
+lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
+  // steps already queued read the descriptor arrays rewritten below (and run
+  // the graph destroyed here): they must have finished first
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  drop_graph(b);
+  struct Launch {
+    lm_batch::Group* g;
+    int count;
+  };
+  std::vector<Launch> launches;
+  for (int i : active) {
+    lm_run* r = b->members[i].run;
+    lm_batch::Group* g = batch_group(b, r->d.N, r->fp32);
+    if (!g) return fail(LM_E_HIP, "batch: stream or event creation failed");
+  }
+  for (auto& g : b->groups) {
+    int count = 0;
+    std::vector<char> bytes = g.fp32 ? group_descs<float>(b, g.N, true, active, &count)
+                                     : group_descs<double>(b, g.N, false, active, &count);
+    if (count == 0) continue;
+    if (bytes.size() > g.cap) {
+      if (g.d_desc) (void)hipFree(g.d_desc);
+      g.d_desc = nullptr;
+      g.cap = 0;
+      if (hipMalloc(&g.d_desc, bytes.size()) != hipSuccess) return fail(LM_E_OOM, "batch: descriptor allocation");
+      g.cap = bytes.size();
+    }
+    HIP_TRY(hipMemcpy(g.d_desc, bytes.data(), bytes.size(), hipMemcpyHostToDevice));
+    launches.push_back({&g, count});
+  }
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  // from here on the capture is always ended, whatever fails
+  hipError_t e = hipEventRecord(b->fork_ev, b->stream);
+  for (auto& l : launches) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(l.g->fork, b->fork_ev, 0);
+    if (e == hipSuccess) {
+      LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(l.g->join, l.g->fork);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, l.g->join, 0);
+  }
+  if (e == hipSuccess) {
+    lm::launch_batch_tick(b->stream, b->d_counters, (int)b->members.size());
+    e = hipGetLastError();
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(LM_E_HIP, std::string("batch capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  b->graph = graph;
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(b);
+    return fail(LM_E_HIP, std::string("batch graph: ") + hipGetErrorString(e));
+  }
+  for (int i : active) b->signature.push_back(b->members[i].run);
+  return LM_OK;
+}
+
+int find_member(const lm_batch* b, const lm_run* r) {
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (b->members[i].run == r) return (int)i;
+  return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_batch_create(void* hip_stream, lm_batch** out) {
+  if (!out) return fail(LM_E_ARG, "null out");
+  lm_batch* b = new lm_batch();
+  b->user = (hipStream_t)hip_stream;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return fail(LM_E_HIP, "batch: stream creation failed");
+  }
+  if (hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(b->stream);
+    delete b;
+    return fail(LM_E_HIP, "batch: event creation failed");
+  }
+  *out = b;
+  return LM_OK;
+}
+
+lm_status lm_batch_add(lm_batch* b, lm_run* r, int32_t steps) {
+  if (!b || !r) return fail(LM_E_ARG, "null argument");
+  if (steps < 0) return fail(LM_E_ARG, "steps < 0");
+  if (r->batch) return fail(LM_E_STATE, "the run already belongs to a batch");
+  if (!r->has_state || !r->in_interval) return fail(LM_E_STATE, "the run needs a state and an open interval");
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  b->members.push_back({r, steps});
+  r->batch = b;
+  drop_graph(b);
+  return LM_OK;
+}
+
+lm_status lm_batch_remove(lm_batch* b, lm_run* r) {
+  if (!b || !r) return fail(LM_E_ARG, "null argument");
+  const int i = find_member(b, r);
+  if (i < 0) return fail(LM_E_ARG, "not a member");
+  b->members.erase(b->members.begin() + i);
+  r->batch = nullptr;
+  drop_graph(b);
+  return LM_OK;
+}
+
+lm_status lm_batch_remaining(lm_batch* b, const lm_run* r, int32_t* remaining) {
+  if (!b || !r || !remaining) return fail(LM_E_ARG, "null argument");
+  const int i = find_member(b, r);
+  if (i < 0) return fail(LM_E_ARG, "not a member");
+  *remaining = b->members[i].remaining;
+  return LM_OK;
+}
+
+lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
+  if (!b) return fail(LM_E_ARG, "null batch");
+  if (max_steps < 0) return fail(LM_E_ARG, "max_steps < 0");
+  const int m = (int)b->members.size();
+  if (m > b->counter_cap) {
+    if (b->d_counters) (void)hipFree(b->d_counters);
+    b->d_counters = nullptr;
+    b->counter_cap = 0;
+    const int cap = std::max(64, 2 * m);
+    if (hipMalloc((void**)&b->d_counters, cap * sizeof(long long)) != hipSuccess)
+      return fail(LM_E_OOM, "batch: counter allocation");
+    b->counter_cap = cap;
+    drop_graph(b);  // descriptors point into the counter array
+  }
+  // the caller's stream and the members' own streams first; then the device
+  // step counters from the host ones
+  HIP_TRY(hipStreamSynchronize(b->user));
+  std::vector<long long> cnt(m);
+  for (int i = 0; i < m; ++i) {
+    HIP_TRY(hipStreamSynchronize(b->members[i].run->stream));
+    cnt[i] = b->members[i].run->n - b->members[i].run->n_tau;
+  }
+  if (m > 0) HIP_TRY(hipMemcpy(b->d_counters, cnt.data(), m * sizeof(long long), hipMemcpyHostToDevice));
+  (void)hipGetLastError();
+  for (int it = 0; it < max_steps; ++it) {
+    std::vector<int> active;
+    for (int i = 0; i < m; ++i)
+      if (b->members[i].remaining > 0) active.push_back(i);
+    if (active.empty()) break;
+    bool same = b->exec && active.size() == b->signature.size();
+    for (size_t j = 0; same && j < active.size(); ++j) same = b->members[active[j]].run == b->signature[j];
+    if (!same) {
+      lm_status s = batch_rebuild(b, active);
+      if (s != LM_OK) return s;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    for (int i : active) {
+      b->members[i].remaining -= 1;
+      b->members[i].run->n += 1;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (active_out) {
+    int a = 0;
+    for (auto& mm : b->members) a += mm.remaining > 0;
+    *active_out = a;
+  }
+  return LM_OK;
+}
+
+lm_status lm_batch_destroy(lm_batch* b) {
+  if (!b) return LM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  for (auto& mm : b->members) mm.run->batch = nullptr;
+  for (auto& g : b->groups) {
+    if (g.d_desc) (void)hipFree(g.d_desc);
+    if (g.fork) (void)hipStreamDestroy(g.fork);
+    if (g.join) (void)hipEventDestroy(g.join);
+  }
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
   return LM_OK;
 }
 

@@ -14,20 +14,6 @@ namespace lm {
 template <int N>
 __global__ void k_drain() {}
 
-template <typename T>
-StepPtrs<T> step_ptrs(RunView& r) {
-  StepPtrs<T> P;
-  P.Yr = (cplx<T>*)r.at(r.L.Yr);
-  P.Yd = (cplx<double>*)r.at(r.L.Yd);
-  P.Ar = (cplx<T>*)r.at(r.L.Ar);
-  P.Ad = (cplx<double>*)r.at(r.L.Ad);
-  P.IC = (cplx<T>*)r.at(r.L.IC);
-  P.RS = (cplx<T>*)r.at(r.L.RS);
-  P.uvhz = (P4<T>*)r.at(r.L.uvhz);
-  P.tw = (const cplx<T>*)r.at(std::is_same<T, double>::value ? r.L.tw64 : r.L.twT);
-  return P;
-}
-
 template <int N>
 dim3 row_grid(int tasks) {
   return dim3(N / RowGeo<N>::RPB, tasks);
@@ -125,6 +111,30 @@ hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms) {
   return launch_steps_profiled_t<double, N>(r, nsteps, ms);
 }
 
+// one RK4 step of every run of one (N, precision) group: blockIdx.z selects
+// the run's descriptor
+template <typename T, int N>
+void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns) {
+  const Dims d = Dims::make(N);
+  for (int stage = 0; stage < 4; ++stage) {
+    dim3 g1 = row_grid<N>(1);
+    g1.z = nruns;
+    hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, dim3(64 * ROW_WAVES), 0, st, desc);
+    dim3 g2 = row_grid<N>(NRT);
+    g2.z = nruns;
+    hipLaunchKernelGGL((k_rows_rhs_b<T, N>), g2, dim3(64 * ROW_WAVES), 0, st, desc, stage);
+    dim3 g3 = col_grid<N>(d, NCG);
+    g3.z = nruns;
+    hipLaunchKernelGGL((k_columns_b<T, N>), g3, col_block<N>(), 0, st, desc, stage);
+  }
+}
+
+template <int N>
+void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32) {
+  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns);
+  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns);
+}
+
 template <int N>
 void launch_steps(RunView& r, int nsteps) {
   if (r.fp32) launch_steps_t<float, N>(r, nsteps);
@@ -163,6 +173,7 @@ void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
 #define LM_INSTANTIATE(N)                                                                \
   namespace lm {                                                                         \
   template void launch_steps<N>(RunView&, int);                                          \
+  template void launch_batch_step<N>(hipStream_t, const void*, int, bool);               \
   template hipError_t launch_steps_profiled<N>(RunView&, int, double*);                  \
   template void launch_prologue<N>(RunView&);                                            \
   template void launch_io_row_forward<N>(RunView&, const IoRowFwd&, int);                \

@@ -7,8 +7,11 @@
 #include <cstddef>
 #include <cstdint>
 
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "layout.hpp"
+#include "step_args.hpp"
 
 namespace lm {
 
@@ -61,5 +64,30 @@ struct RunView {
   int ys_cur;        // which stage-value buffer holds the current stage input
   void* at(size_t off) const { return slab + off; }
 };
+
+template <typename T>
+StepPtrs<T> step_ptrs(RunView& r) {
+  StepPtrs<T> P;
+  P.Yr = (cplx<T>*)r.at(r.L.Yr);
+  P.Yd = (cplx<double>*)r.at(r.L.Yd);
+  P.Ar = (cplx<T>*)r.at(r.L.Ar);
+  P.Ad = (cplx<double>*)r.at(r.L.Ad);
+  P.IC = (cplx<T>*)r.at(r.L.IC);
+  P.RS = (cplx<T>*)r.at(r.L.RS);
+  P.uvhz = (P4<T>*)r.at(r.L.uvhz);
+  P.tw = (const cplx<T>*)r.at(std::is_same<T, double>::value ? r.L.tw64 : r.L.twT);
+  return P;
+}
+
+template <typename T>
+RunDesc<T> run_desc(RunView& r, const long long* counter) {
+  RunDesc<T> D;
+  D.P = step_ptrs<T>(r);
+  D.ph = r.ph;
+  D.Ys0 = (cplx<T>*)r.at(r.L.Ys0);
+  D.Ys1 = (cplx<T>*)r.at(r.L.Ys1);
+  D.counter = counter;
+  return D;
+}
 
 }  // namespace lm

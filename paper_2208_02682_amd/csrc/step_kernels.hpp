@@ -34,25 +34,9 @@
 
 #include "fft_core.hpp"
 #include "layout.hpp"
+#include "step_args.hpp"
 
 namespace lm {
-
-template <typename T>
-struct alignas(4 * sizeof(T)) P4 {
-  T u, v, h, z;
-};
-
-template <typename T>
-struct StepPtrs {
-  cplx<T>* Yr;        // [NSF_R][NKX][NKY] state, working precision
-  cplx<double>* Yd;   // [NSF_D][NKX][NKY] state, float64
-  cplx<T>* Ar;        // RK4 accumulators, same shapes
-  cplx<double>* Ad;
-  cplx<T>* IC;        // [NIC][N][NKXP] column-pass outputs
-  cplx<T>* RS;        // [NRS][N][NKXP] row-pass outputs
-  P4<T>* uvhz;        // [N][N] physical u, v, h, zeta
-  const cplx<T>* tw;  // [N] exp(-2 pi i m / N)
-};
 
 constexpr int ROW_WAVES = 4;  // wavefronts per row-kernel block
 
@@ -150,14 +134,16 @@ __device__ __forceinline__ int wrapN(int i, int N) { return (i + N) % N; }
 // all tasks of neighbouring rows / column tiles meet in the same L2 (the
 // gathers, re-read rows and shared 128-byte lines hit in L2).
 constexpr int NUM_XCD = 8;
-__device__ __forceinline__ void xcd_split(int nslow, int nfast, int& slow, int& fast) {
-  const int total = nslow * nfast;
-  const int b = blockIdx.y * gridDim.x + blockIdx.x;
+__device__ __forceinline__ void xcd_split(int nslow, int nfast, int& slow, int& fast, int& z) {
+  const int total = nslow * nfast * gridDim.z;
+  const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const int q = total / NUM_XCD, r = total % NUM_XCD;
   const int xcd = b % NUM_XCD;
   const int logical = xcd * q + min(xcd, r) + b / NUM_XCD;
   fast = logical % nfast;
-  slow = logical / nfast;
+  const int rest = logical / nfast;
+  slow = rest % nslow;
+  z = rest / nslow;
 }
 
 // periodic bilinear interpolation of the interleaved physical fields at x + xi
@@ -188,13 +174,10 @@ __device__ __forceinline__ P4<T> gather4(const P4<T>* __restrict__ F, int x, int
 // rows_dyn
 // --------------------------------------------------------------------------
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d) {
+__device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& d, int rowblock, cplx<T>* lds) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
-  __shared__ cplx<T> lds[G::RPB * G::L];
   const int grp = row_group<NT>(), t = threadIdx.x % NT;
-  int rowblock, unused;
-  xcd_split(gridDim.x * gridDim.y, 1, rowblock, unused);
   const int y = rowblock * G::RPB + grp;  // the grid covers the rows exactly
   cplx<T>* buf = lds + grp * G::L;
   const size_t rf = d.rowfield_elems();
@@ -244,6 +227,14 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims
   forward_row<T, N, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
 }
 
+template <typename T, int N>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d) {
+  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+  int rowblock, unused, z;
+  xcd_split(gridDim.x, 1, rowblock, unused, z);
+  rows_dyn_body<T, N>(P, d, rowblock, lds);
+}
+
 // --------------------------------------------------------------------------
 // rows_rhs
 // --------------------------------------------------------------------------
@@ -255,13 +246,11 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims
 //   RT_P   strategy 1, both P components (eq. (3.9) in P form)
 // The two strategy-2 tasks each transform xi and gather at x + xi.
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s) {
+__device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
+                                              int task, cplx<T>* lds) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
-  __shared__ cplx<T> lds[G::RPB * G::L];
   const int grp = row_group<NT>(), t = threadIdx.x % NT;
-  int rowblock, task;
-  xcd_split(gridDim.x, gridDim.y, rowblock, task);  // grid = (row blocks, tasks)
   const int y = rowblock * G::RPB + grp;  // the grid covers the rows exactly
   cplx<T>* buf = lds + grp * G::L;
   const size_t rf = d.rowfield_elems();
@@ -342,6 +331,14 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims
     const int o = gt ? RS_GTH : RS_PX;
     forward_row<T, N, true>(a, buf, t, P.tw, RSr + o * rf, RSr + (o + 1) * rf);
   }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s) {
+  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+  int rowblock, task, z;
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);  // grid = (row blocks, tasks)
+  rows_rhs_body<T, N>(P, d, s, rowblock, task, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -567,18 +564,16 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
 
 // stage >= 0: RK4 stage; stage < 0: only transform the current state (prologue)
 template <typename T, int N>
-__global__ void __launch_bounds__(col_threads<N>())
-    k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out) {
+__device__ __forceinline__ void columns_body(const StepPtrs<T>& P, const Dims& d, const Phys& ph, int stage,
+                                             const cplx<T>* Ys_in, cplx<T>* Ys_out, int tile, int group,
+                                             cplx<T>* lds) {
   constexpr int C = col_tile<N>();
   constexpr int E = fft_E<N>(), NT = N / E, LC = col_buf(N);
-  __shared__ cplx<T> lds[C * LC];
   ColCtx<T, N, C> cx;
   cx.lds = lds;
   cx.c = threadIdx.x / NT;
   cx.t = threadIdx.x % NT;
   cx.buf = lds + cx.c * LC;
-  int tile, group;
-  xcd_split(gridDim.x, gridDim.y, tile, group);  // grid = (column tiles, field groups)
   cx.kx0 = tile * C;
   cx.kx = cx.kx0 + cx.c;
   cx.valid = cx.kx <= kcut<N>();
@@ -596,6 +591,52 @@ __global__ void __launch_bounds__(col_threads<N>())
     case CG_PY: column_group<T, N, C, CG_PY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
     default: break;
   }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(col_threads<N>())
+    k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out) {
+  __shared__ cplx<T> lds[col_tile<N>() * col_buf(N)];
+  int tile, group, z;
+  xcd_split(gridDim.x, gridDim.y, tile, group, z);  // grid = (column tiles, field groups)
+  columns_body<T, N>(P, d, ph, stage, Ys_in, Ys_out, tile, group, lds);
+}
+
+// --------------------------------------------------------------------------
+// batched entry points: blockIdx.z selects a run of one (N, precision) group
+// --------------------------------------------------------------------------
+
+template <typename T, int N>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn_b(const RunDesc<T>* __restrict__ runs) {
+  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+  int rowblock, unused, z;
+  xcd_split(gridDim.x, 1, rowblock, unused, z);
+  rows_dyn_body<T, N>(runs[z].P, Dims::make(N), rowblock, lds);
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>* __restrict__ runs, int stage) {
+  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+  int rowblock, task, z;
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);
+  const RunDesc<T>& R = runs[z];
+  // time since the interval start, from integers (as the single-run path)
+  const double c = (stage == 0) ? 0.0 : ((stage == 3) ? 1.0 : 0.5);
+  const double s = (double(*R.counter) + c) * R.ph.dt;
+  rows_rhs_body<T, N>(R.P, Dims::make(N), s, rowblock, task, lds);
+}
+
+// stage parity selects the stage-value buffers: between steps the current
+// stage input is always Ys0 (four swaps per step)
+template <typename T, int N>
+__global__ void __launch_bounds__(col_threads<N>()) k_columns_b(const RunDesc<T>* __restrict__ runs, int stage) {
+  __shared__ cplx<T> lds[col_tile<N>() * col_buf(N)];
+  int tile, group, z;
+  xcd_split(gridDim.x, gridDim.y, tile, group, z);
+  const RunDesc<T>& R = runs[z];
+  const cplx<T>* Ys_in = (stage & 1) ? R.Ys1 : R.Ys0;
+  cplx<T>* Ys_out = (stage & 1) ? R.Ys0 : R.Ys1;
+  columns_body<T, N>(R.P, Dims::make(N), R.ph, stage, Ys_in, Ys_out, tile, group, lds);
 }
 
 }  // namespace lm

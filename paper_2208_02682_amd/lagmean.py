@@ -74,6 +74,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_peek": [P, ctypes.c_int32, P, ctypes.c_int],
         "lm_counters": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "lm_destroy": [P],
+        "lm_batch_create": [P, ctypes.POINTER(P)],
+        "lm_batch_add": [P, P, ctypes.c_int32],
+        "lm_batch_remove": [P, P],
+        "lm_batch_step": [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+        "lm_batch_remaining": [P, P, ctypes.POINTER(ctypes.c_int32)],
+        "lm_batch_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -203,3 +209,54 @@ class Run:
         a, b = ctypes.c_int64(0), ctypes.c_int64(0)
         _check(self.lib.lm_counters(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+
+class Batch:
+    """Runs of any N and precision advanced together (wraps lm_batch).
+
+    A member needs a state and an open interval; it is advanced by up to its
+    step budget.  While a member, a run is driven only through the batch."""
+
+    def __init__(self, stream: int = 0):
+        self.lib = load_library()
+        self.h = ctypes.c_void_p(0)
+        self.members = []
+        _check(self.lib.lm_batch_create(ctypes.c_void_p(stream), ctypes.byref(self.h)))
+
+    def add(self, run: Run, steps: int) -> None:
+        _check(self.lib.lm_batch_add(self.h, run.h, int(steps)))
+        self.members.append(run)
+
+    def remove(self, run: Run) -> None:
+        _check(self.lib.lm_batch_remove(self.h, run.h))
+        self.members.remove(run)
+
+    def step(self, max_steps: int) -> int:
+        """Advance every member by min(max_steps, its budget); returns how many
+        members still have budget left."""
+        active = ctypes.c_int32(0)
+        _check(self.lib.lm_batch_step(self.h, int(max_steps), ctypes.byref(active)))
+        return active.value
+
+    def remaining(self, run: Run) -> int:
+        r = ctypes.c_int32(0)
+        _check(self.lib.lm_batch_remaining(self.h, run.h, ctypes.byref(r)))
+        return r.value
+
+    def close(self) -> None:
+        if self.h and self.h.value:
+            _check(self.lib.lm_batch_destroy(self.h))
+            self.h = ctypes.c_void_p(0)
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
