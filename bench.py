@@ -14,6 +14,15 @@ Prints one JSON line with the driver's keys plus
   cpu_baseline : the float64 CPU oracle on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Two more modes print one JSON line each:
+  --mode batch : 64 independent runs of uneven N (128..512, float32 transforms)
+                 advanced together by one lm_batch, against the same runs one
+                 after another alone and as plain float64 runs;
+  --mode serve : Poisson arrivals of averaging requests (N in 128..1024) served
+                 with admission by HBM footprint and continuous batching: p50/p99
+                 latency from arrival to means on the host, at the offered rate
+                 and at a sustainable rate (offered load 0.7 of the measured capacity).
 """
 
 from __future__ import annotations
@@ -103,6 +112,209 @@ def cpu_baseline(w, seconds: float):
                       f"({el:.1f} s, scipy.fft with {threads} threads)"}
 
 
+def _initial_state(w):
+    return w.initial_state()
+
+
+def generate_states(workloads, workers: int = 16):
+    """Initial states of the requests, made on the host before any clock starts
+    (worker processes; the GPU is not touched)."""
+    import concurrent.futures
+    import multiprocessing
+    n = max(1, min(workers, os.cpu_count() or 1))
+    with concurrent.futures.ProcessPoolExecutor(n, mp_context=multiprocessing.get_context("spawn")) as ex:
+        return list(ex.map(_initial_state, workloads, chunksize=4))
+
+
+def _cfg(w, precision=None):
+    from paper_2208_02682_amd import make_config
+    return make_config(w.N, precision=precision or w.precision, f=w.f, g=w.g, H=w.H, dt=w.dt, nu8=w.nu8)
+
+
+def bench_batch(a) -> dict:
+    """Config of 64 uneven runs: batched against alone, and against float64 alone."""
+    import numpy as np
+    import torch
+    from paper_2208_02682_amd import Batch, OUTPUTS, Run
+    from synth.workloads import batch_workloads
+
+    ws = batch_workloads(a.batch_runs)
+    states = generate_states(ws)
+    torch.cuda.set_device(0)
+    pts = sum(w.N * w.N * w.steps_per_interval for w in ws)
+
+    def start(run, st):
+        run.set_state(*st)
+        run.begin_interval()
+
+    # warm-up of every distinct configuration (first launches, allocations)
+    for prec in ("fp32", "fp64"):
+        seen = set()
+        for w, st in zip(ws, states):
+            if w.N in seen:
+                continue
+            seen.add(w.N)
+            with Run(_cfg(w, prec)) as r:
+                start(r, st)
+                r.step(2)
+                r.end_interval()
+
+    # batched: every run resident, one lm_batch until all budgets are spent,
+    # then each interval closed (the division by T and the output transforms)
+    runs = [Run(_cfg(w)) for w in ws]
+    for r, st in zip(runs, states):
+        start(r, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with Batch() as b:
+        for r, w in zip(runs, ws):
+            b.add(r, w.steps_per_interval)
+        while b.step(a.tick_steps):
+            pass
+        for r in runs:
+            b.remove(r)
+    for r in runs:
+        r.end_interval()
+    t_batch = time.perf_counter() - t0
+    batched = [r.outputs() for r in runs]
+    for r in runs:
+        r.close()
+
+    def sequential(prec, compare):
+        total = 0.0
+        same = True
+        for i, (w, st) in enumerate(zip(ws, states)):
+            with Run(_cfg(w, prec)) as r:
+                start(r, st)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r.step(w.steps_per_interval)
+                r.end_interval()
+                total += time.perf_counter() - t
+                if compare:
+                    o = r.outputs()
+                    same = same and all(np.array_equal(o[k], batched[i][k]) for k in OUTPUTS)
+        return total, same
+
+    print(f"batch: {len(ws)} runs batched in {t_batch:.2f} s", file=sys.stderr, flush=True)
+    t_alone, identical = sequential("fp32", True)
+    print(f"batch: the same runs alone in {t_alone:.2f} s", file=sys.stderr, flush=True)
+    t_fp64, _ = sequential("fp64", False)
+    print(f"batch: float64 runs alone in {t_fp64:.2f} s", file=sys.stderr, flush=True)
+    sizes = sorted({w.N for w in ws})
+    return {
+        "metric": f"aggregate grid-pt RK4 steps/s, {len(ws)} uneven runs batched", "value": pts / t_batch,
+        "unit": "grid-pt RK4 steps/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(ws)} independent runs, N in {sizes}, float32 transforms with float64 "
+                               f"xi and P, Ro ~ U[0.02, 0.2], wave/vortex energy ratio log-U[0.25, 4], "
+                               f"T ~ U[1, 8] wave periods, dt = 0.64/N",
+                   "runs": len(ws), "total_steps": sum(w.steps_per_interval for w in ws),
+                   "grid_point_steps": pts, "tick_steps": a.tick_steps},
+        "seconds": {"batched": t_batch, "alone_sequential": t_alone, "fp64_alone_sequential": t_fp64},
+        "alone_sequential_value": pts / t_alone, "fp64_alone_sequential_value": pts / t_fp64,
+        "speedup_vs_alone": t_alone / t_batch, "speedup_vs_fp64_alone": t_fp64 / t_batch,
+        "batched_identical_to_alone": identical,
+    }
+
+
+def _serve_once(reqs, states, rate, window, a, t_limit):
+    """Real-time serving of one arrival sequence; returns the per-request timings."""
+    import numpy as np
+    from paper_2208_02682_amd.serve import Job, Server
+
+    server = Server(a.hbm_budget_gib * 2**30, max_resident_points=a.max_resident_points,
+                    tick_steps=a.tick_steps)
+    # resident state: one run of every configuration created and warmed up
+    # before the clock starts (later requests reuse pooled runs)
+    seen = {}
+    for r, st in zip(reqs, states):
+        seen.setdefault(r.run.N, (r.run, st))
+    for i, (w, st) in enumerate(seen.values()):
+        server.submit(Job(-1 - i, _cfg(w), st, 2, arrival=server.clock()))
+    while server.busy():
+        server.tick()
+    done, lat = [], {}
+    busy = 0.0
+    t0 = time.perf_counter()
+    i = 0
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        if now > t_limit:
+            break
+        while i < len(reqs) and reqs[i].arrival <= now:
+            r = reqs[i]
+            server.submit(Job(r.index, _cfg(r.run), states[i], r.run.steps_per_interval, arrival=t0 + r.arrival))
+            states[i] = None
+            i += 1
+        if not server.busy():
+            if i < len(reqs):
+                time.sleep(max(0.0, min(reqs[i].arrival - (time.perf_counter() - t0), 0.05)))
+            continue
+        tb = time.perf_counter()
+        for j in server.tick():
+            if j.error is not None:
+                raise RuntimeError(f"request {j.id}: {j.error}")
+            j.outputs = None  # the means reached the host; the benchmark does not keep them
+            done.append(j)
+            lat[j.id] = j.latency
+            if len(done) % 50 == 0:
+                print(f"serve: {len(done)}/{len(reqs)} requests done at {time.perf_counter() - t0:.1f} s, "
+                      f"{len(server.queue)} queued, {len(server.active)} resident", file=sys.stderr, flush=True)
+        busy += time.perf_counter() - tb
+    elapsed = time.perf_counter() - t0
+    stats = {"created_runs": server.created, "released_runs": server.evicted}
+    server.close()
+    size = {r.index: r.run.N * r.run.N * r.run.steps_per_interval for r in reqs}
+    served = sum(size[j.id] for j in done)
+    offered = sum(size.values()) / window
+    capacity = served / busy if busy > 0 else float("nan")
+    all_lat = np.array([lat.get(r.index, np.inf) for r in reqs])
+    got = np.array(sorted(lat.values()))
+
+    def pct(x, q):
+        v = float(np.percentile(x, q)) if len(x) else float("nan")
+        return v if np.isfinite(v) else None
+    in_window = sum(1 for j in done if j.finished - t0 <= window)
+    return {"rate_per_s": rate, "window_s": window, "requests": len(reqs), "completed": len(done),
+            "completed_fraction": len(done) / len(reqs), "completed_within_window_fraction": in_window / len(reqs),
+            "p50_latency_s": pct(all_lat, 50), "p99_latency_s": pct(all_lat, 99),
+            "p50_latency_completed_s": pct(got, 50), "p99_latency_completed_s": pct(got, 99),
+            "mean_latency_completed_s": float(got.mean()) if len(got) else None,
+            "elapsed_s": elapsed, "offered_pt_steps_per_s": offered, "served_pt_steps_per_s": served / elapsed,
+            "capacity_pt_steps_per_s": capacity, "rho": offered / capacity, **stats}
+
+
+def bench_serve(a) -> dict:
+    import numpy as np
+    import torch
+    from synth.workloads import serving_requests
+
+    reqs = serving_requests(rate=a.rate, duration=a.window, seed=7)
+    sizes = sorted({r.run.N for r in reqs})
+    states = generate_states([r.run for r in reqs])
+    print(f"serve: {len(reqs)} request states generated", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    mean_work = float(np.mean([r.run.N * r.run.N * r.run.steps_per_interval for r in reqs]))
+    main = _serve_once(reqs, states, a.rate, a.window, a, a.window + a.drain_limit)
+    rec = {"metric": "p50/p99 solve latency (arrival to means on the host), Poisson arrivals",
+           "value": main["p99_latency_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"averaging requests, N in {sizes} with probabilities 0.4/0.3/0.2/0.1, the "
+                                  f"64^2 recipe scaled to N, float32 transforms with float64 xi and P, "
+                                  f"T ~ U[1, 8] wave periods, dt = 0.64/N, arrival seed 7",
+                      "mean_grid_point_steps_per_request": mean_work, "hbm_budget_gib": a.hbm_budget_gib,
+                      "max_resident_points": a.max_resident_points, "tick_steps": a.tick_steps},
+           "offered": main}
+    if a.sustainable_window > 0 and np.isfinite(main["capacity_pt_steps_per_s"]):
+        rate = 0.7 * main["capacity_pt_steps_per_s"] / mean_work
+        reqs2 = serving_requests(rate=rate, duration=a.sustainable_window, seed=7)
+        states2 = generate_states([r.run for r in reqs2])
+        rec["sustainable"] = _serve_once(reqs2, states2, rate, a.sustainable_window, a,
+                                         a.sustainable_window + a.drain_limit)
+    return rec
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +325,17 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed replay (roofline fields become null)")
+    ap.add_argument("--mode", choices=("step", "batch", "serve"), default="step")
+    ap.add_argument("--batch-runs", type=int, default=64)
+    ap.add_argument("--tick-steps", type=int, default=32, help="batch/serve: steps per lm_batch_step call")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--window", type=float, default=30.0, help="serve: seconds of arrivals")
+    ap.add_argument("--sustainable-window", type=float, default=60.0,
+                    help="serve: seconds of arrivals at 0.7 of the measured capacity (0 = skip)")
+    ap.add_argument("--drain-limit", type=float, default=300.0,
+                    help="serve: seconds after the last arrival before unfinished requests are counted as such")
+    ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
+    ap.add_argument("--max-resident-points", type=int, default=8 * 1024 * 1024)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -122,6 +345,10 @@ def main(argv=None) -> int:
               f"--gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
 
+    if a.mode in ("batch", "serve"):
+        rec = bench_batch(a) if a.mode == "batch" else bench_serve(a)
+        print(json.dumps(rec), flush=True)
+        return 0
     import numpy as np
     import torch
     if a.copy_probe:

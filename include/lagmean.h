@@ -175,8 +175,9 @@ lm_status lm_destroy(lm_run* run);
  * group's runs (blockIdx.z selects the run), groups are parallel branches of
  * the graph.  Each member computes exactly what it computes alone (same
  * kernels, same arithmetic, no cross-run reductions), bit for bit.
- * A member must not be used through the single-run calls, or destroyed,
- * while it belongs to a batch.
+ * While a run belongs to a batch, lm_set_state, lm_begin_interval, lm_step,
+ * lm_step_profiled, lm_end_interval and lm_destroy return LM_E_STATE for it;
+ * the reading calls stay available between lm_batch_step calls.
  * ------------------------------------------------------------------------- */
 typedef struct lm_batch lm_batch;
 

@@ -205,6 +205,7 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
 
 lm_status lm_set_state(lm_run* r, const double* u, const double* v, const double* h, int on_device) {
   if (!r || !u || !v || !h) return fail(LM_E_ARG, "null argument");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   const size_t nn = (size_t)r->d.N * r->d.N;
   double* phys = (double*)r->at(r->L.phys);
   lm_status s;
@@ -266,6 +267,7 @@ lm_status lm_get_state(lm_run* r, double* u, double* v, double* h, int on_device
 
 lm_status lm_begin_interval(lm_run* r) {
   if (!r) return fail(LM_E_ARG, "null run");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
   lm_status s;
   if ((s = zero_means(r)) != LM_OK) return s;
@@ -278,6 +280,7 @@ lm_status lm_begin_interval(lm_run* r) {
 
 lm_status lm_step(lm_run* r, int32_t nsteps) {
   if (!r) return fail(LM_E_ARG, "null run");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   if (nsteps < 0) return fail(LM_E_ARG, "nsteps < 0");
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
   LM_DISPATCH_N(r->d.N, lm::launch_steps, *r, nsteps);
@@ -286,6 +289,7 @@ lm_status lm_step(lm_run* r, int32_t nsteps) {
 
 lm_status lm_step_profiled(lm_run* r, int32_t nsteps, double* ms_avg) {
   if (!r || !ms_avg) return fail(LM_E_ARG, "null argument");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   if (nsteps <= 0 || nsteps > 4096) return fail(LM_E_ARG, "nsteps must be in 1..4096");
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
   double ms[3] = {0.0, 0.0, 0.0};
@@ -300,6 +304,7 @@ lm_status lm_step_profiled(lm_run* r, int32_t nsteps, double* ms_avg) {
 
 lm_status lm_end_interval(lm_run* r, double* T_out) {
   if (!r) return fail(LM_E_ARG, "null run");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   if (!r->in_interval) return fail(LM_E_STATE, "no open interval");
   if (r->n == r->n_tau) return fail(LM_E_STATE, "interval holds no step");
   const double T = double(r->n - r->n_tau) * r->ph.dt;

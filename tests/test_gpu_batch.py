@@ -99,6 +99,11 @@ def test_batch_rules():
     with pytest.raises(LagMeanError) as e:
         run.close()                   # cannot destroy a member
     assert e.value.status == -2
+    for call in (lambda: run.step(1), run.begin_interval, run.end_interval, lambda: run.set_state(u, v, h)):
+        with pytest.raises(LagMeanError) as e:
+            call()                    # nor drive it through the single-run calls
+        assert e.value.status == -2
+    assert run.counters() == (0, 0)   # reading is allowed
     assert b.step(100) == 0
     assert run.counters() == (3, 3)
     b.close()
