@@ -17,6 +17,8 @@
 // m = r (j mod Ns) N / (Ns R) < N.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 namespace lm {
@@ -253,10 +255,15 @@ __device__ __forceinline__ void xsync() {
   else wave_sync();
 }
 
+// the twiddle table lives in global memory: loads through this pointer type
+// are global (not generic) loads, which do not hold up the LDS counter
+template <typename T>
+using gptr = const __attribute__((address_space(1))) cplx<T>*;
+
 // one Stockham stage of radix R after sub-transforms of length Ns (Ns > 1),
-// reading and writing the group's LDS buffer
-template <typename T, int N, int E, int DIR, int Ns, int R>
-__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, const cplx<T>* __restrict__ tw) {
+// reading and writing the group's LDS buffer; TW is the twiddle pointer type
+template <typename T, int N, int E, int DIR, int Ns, int R, typename TW>
+__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, TW tw) {
   constexpr int NT = N / E;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "radix must divide E");
@@ -274,7 +281,8 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, const cplx<T
     const int k = j % Ns;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      const cplx<T> w = tw[r * k * (N / (Ns * R))];
+      const int m = r * k * (N / (Ns * R));
+      const cplx<T> w = {tw[m].x, tw[m].y};
       v[b * R + r] = (DIR < 0) ? cmul(v[b * R + r], w) : cmulc(v[b * R + r], w);
     }
     dft<R, DIR>(&v[b * R]);
@@ -288,21 +296,25 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, const cplx<T
 // Full transform of N points held by NT = N / E lanes.  v: lane t holds
 // x[t + NT e]; buf: the group's LDS buffer (padded_len(N) slots).  On exit the
 // spectrum is in buf in natural order.  DIR = -1: forward (exp(-i...)),
-// DIR = +1: inverse (unnormalised).
-template <typename T, int N, int E, int DIR>
+// DIR = +1: inverse (unnormalised).  GTW: read the twiddles with global loads
+// (else generic ones, which also count against the LDS counter: measured
+// faster in the dynamics row pass, slower in the others).
+template <typename T, int N, int E, int DIR, bool GTW = true>
 __device__ __forceinline__ void fft(cplx<T> (&v)[E], cplx<T>* buf, int t, const cplx<T>* __restrict__ tw) {
   using PL = Plan<N, E>;
   constexpr int NT = N / E;
   // a fresh view of the twiddle table for every transform: stops the compiler
   // from keeping twiddles of one transform live until the next one
   asm volatile("" : "+s"(tw));
+  using TW = typename std::conditional<GTW, gptr<T>, const cplx<T>*>::type;
+  const TW ptw = (TW)tw;
   dft<E, DIR>(v);
 #pragma unroll
   for (int r = 0; r < E; ++r) buf[pidx(t * E + r)] = v[r];
   xsync<NT>();
-  if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, tw);
-  if constexpr (PL::R3 > 1) stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, tw);
-  if constexpr (PL::R4 > 1) stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, tw);
+  if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, ptw);
+  if constexpr (PL::R3 > 1) stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, ptw);
+  if constexpr (PL::R4 > 1) stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, ptw);
 }
 
 }  // namespace lm

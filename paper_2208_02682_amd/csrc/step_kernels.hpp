@@ -96,11 +96,11 @@ __device__ __forceinline__ void load_pair(cplx<T> (&z)[fft_E<N>()], const cplx<T
 }
 
 // Inverse-transform a pair and leave lane values p[e] at x = t + NT e.
-template <typename T, int N>
+template <typename T, int N, bool GTW = true>
 __device__ __forceinline__ void inverse_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* buf, int t,
                                             const cplx<T>* __restrict__ tw) {
   constexpr int E = fft_E<N>(), NT = N / E;
-  fft<T, N, E, +1>(z, buf, t, tw);
+  fft<T, N, E, +1, GTW>(z, buf, t, tw);
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = buf[pidx(t + NT * e)];
   xsync<NT>();
@@ -109,13 +109,16 @@ __device__ __forceinline__ void inverse_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* b
 
 // Forward-transform z = a + i b (lane values at x = t + NT e) and store the
 // half spectra of a and b (kx = 0..K) to the row pointers OA and OB.
-template <typename T, int N, bool TWO>
+template <typename T, int N, bool TWO, bool GTW = true>
 __device__ __forceinline__ void forward_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* buf, int t,
                                             const cplx<T>* __restrict__ tw,
                                             cplx<T>* __restrict__ OA, cplx<T>* __restrict__ OB) {
   constexpr int E = fft_E<N>(), NT = N / E, K = kcut<N>();
-  fft<T, N, E, -1>(z, buf, t, tw);
-  for (int k = t; k <= K; k += NT) {
+  fft<T, N, E, -1, GTW>(z, buf, t, tw);
+#pragma unroll
+  for (int r = 0; r < (K + NT) / NT; ++r) {
+    const int k = t + NT * r;
+    if (k > K) break;
     const cplx<T> zk = buf[pidx(k)];
     const cplx<T> zm = buf[pidx(k == 0 ? 0 : N - k)];
     OA[k] = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
@@ -126,6 +129,17 @@ __device__ __forceinline__ void forward_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* b
 }
 
 __device__ __forceinline__ int wrapN(int i, int N) { return (i + N) % N; }
+
+// i in [-N, 2N) to [0, N): a mask for powers of two, two selects otherwise
+template <int N>
+__device__ __forceinline__ int wrap2N(int i) {
+  if constexpr ((N & (N - 1)) == 0) {
+    return i & (N - 1);
+  } else {
+    i = (i < 0) ? i + N : i;
+    return (i >= N) ? i - N : i;
+  }
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
 // Renumber the flattened block index so that every XCD receives a contiguous
@@ -144,6 +158,36 @@ __device__ __forceinline__ void xcd_split(int nslow, int nfast, int& slow, int& 
   const int rest = logical / nfast;
   slow = rest % nslow;
   z = rest / nslow;
+}
+
+// periodic bilinear interpolation at x + xi of one pair of the interleaved
+// physical fields: (u, v) if PAIR == 0, (eta, zeta) if PAIR == 1 (8 bytes per
+// corner instead of the whole 16-byte point)
+template <typename T, int N, int PAIR>
+__device__ __forceinline__ cplx<T> gather2(const P4<T>* __restrict__ F, int x, int y, T xix, T xiy) {
+  const T scl = T(double(N) / 6.283185307179586476925286766559);
+  T ox = xix * scl, oy = xiy * scl;
+  T fx = floor(ox), fy = floor(oy);
+  // keep indices in range even for non-finite displacements
+  fx = fmin(fmax(fx, T(-N)), T(N));
+  fy = fmin(fmax(fy, T(-N)), T(N));
+  const T ax = ox - fx, ay = oy - fy;
+  // x + fx and y + fy lie in [-N, 2N)
+  const int ix0 = wrap2N<N>(x + int(fx)), iy0 = wrap2N<N>(y + int(fy));
+  const int ix1 = (ix0 + 1 == N) ? 0 : ix0 + 1, iy1 = (iy0 + 1 == N) ? 0 : iy0 + 1;
+  // uniform base plus 32-bit byte offsets (the field is far below 4 GiB)
+  const char* F2 = reinterpret_cast<const char*>(F) + PAIR * sizeof(cplx<T>);
+  constexpr unsigned PT = sizeof(P4<T>), ROW = N * sizeof(P4<T>);
+  const unsigned r0 = unsigned(iy0) * ROW, r1 = unsigned(iy1) * ROW;
+  const unsigned c0 = unsigned(ix0) * PT, c1 = unsigned(ix1) * PT;
+  const cplx<T> f00 = *reinterpret_cast<const cplx<T>*>(F2 + (r0 + c0));
+  const cplx<T> f01 = *reinterpret_cast<const cplx<T>*>(F2 + (r0 + c1));
+  const cplx<T> f10 = *reinterpret_cast<const cplx<T>*>(F2 + (r1 + c0));
+  const cplx<T> f11 = *reinterpret_cast<const cplx<T>*>(F2 + (r1 + c1));
+  const T w00 = (T(1) - ax) * (T(1) - ay), w01 = ax * (T(1) - ay);
+  const T w10 = (T(1) - ax) * ay, w11 = ax * ay;
+  return {w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x,
+          w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y};
 }
 
 // periodic bilinear interpolation of the interleaved physical fields at x + xi
@@ -186,7 +230,7 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
 
   cplx<T> uv[E], hz[E];
   load_pair<T, N, false, false>(uv, ICr + IC_U * rf, ICr + IC_V * rf, t);
-  inverse_row<T, N>(uv, buf, t, P.tw);
+  inverse_row<T, N, false>(uv, buf, t, P.tw);
   // (eta + i zeta): zeta spectrum = i kx C_v - C_uy
   {
     const cplx<T>* Ch = ICr + IC_H * rf;
@@ -207,7 +251,7 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
       hz[r] = (lo || hi) ? cplx<T>{a.x - b.y, a.y + b.x} : cplx<T>{T(0), T(0)};
     }
   }
-  inverse_row<T, N>(hz, buf, t, P.tw);
+  inverse_row<T, N, false>(hz, buf, t, P.tw);
 
   P4<T>* out = P.uvhz + (size_t)y * N;
 #pragma unroll
@@ -217,14 +261,14 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
   cplx<T> z[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
-  forward_row<T, N, true>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
+  forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
 #pragma unroll
   for (int e = 0; e < E; ++e)
     z[e] = {T(0.5) * (uv[e].x * uv[e].x + uv[e].y * uv[e].y), hz[e].x * uv[e].x};  // K, eta u
-  forward_row<T, N, true>(z, buf, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
+  forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = {hz[e].x * uv[e].y, T(0)};  // eta v
-  forward_row<T, N, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
+  forward_row<T, N, false, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
 }
 
 template <typename T, int N>
@@ -282,14 +326,23 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
     constexpr int GG = 4;
     static_assert(E % GG == 0, "gather groups");
     const bool xi_task = (task == RT_XI);
+    if (xi_task) {
 #pragma unroll
-    for (int e0 = 0; e0 < E; e0 += GG) {
+      for (int e0 = 0; e0 < E; e0 += GG) {
 #pragma unroll
-      for (int e = e0; e < e0 + GG; ++e) {
-        const P4<T> g = gather4<T, N>(F, t + NT * e, y, a[e].x, a[e].y);
-        a[e] = xi_task ? cplx<T>{g.u - w[e].x, g.v - w[e].y} : cplx<T>{g.h, g.z};
+        for (int e = e0; e < e0 + GG; ++e) {
+          const cplx<T> g = gather2<T, N, 0>(F, t + NT * e, y, a[e].x, a[e].y);
+          a[e] = {g.x - w[e].x, g.y - w[e].y};
+        }
+        sched_fence();
       }
-      sched_fence();
+    } else {
+#pragma unroll
+      for (int e0 = 0; e0 < E; e0 += GG) {
+#pragma unroll
+        for (int e = e0; e < e0 + GG; ++e) a[e] = gather2<T, N, 1>(F, t + NT * e, y, a[e].x, a[e].y);
+        sched_fence();
+      }
     }
     // minus w . grad of (xi_x, xi_y) or of (g-bar_h, g-bar_zeta)
     const int f1 = xi_task ? IC_XIX : IC_GBH, f2 = xi_task ? IC_XIY : IC_GBZ;
@@ -444,7 +497,8 @@ __device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const 
     if (DY) q = {-T(ky) * q.y, T(ky) * q.x};
     v[r] = q;
   }
-  __syncthreads();  // the tile buffers may still be read by the previous store
+  // no barrier: since the last block-wide tile access (which ends with one)
+  // only this wavefront has touched its buffer
   fft<T, N, fft_E<N>(), +1>(v, cx.buf, cx.t, tw);
   tile_store<T, N, C>(cx, dst, d);
 }

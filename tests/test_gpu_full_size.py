@@ -20,29 +20,48 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _compare(name, tol):
+def _errors(name, precision=None, perturb=None):
+    """Per interval and output: relative L2 error of a GPU run of the workload
+    (optionally in another precision, from a perturbed initial state) against
+    the stored float64 oracle values."""
     from synth import workload
     path = os.path.join(GOLDEN, f"{name}.npz")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated")
     g = np.load(path)
     w = workload(name)
+    if precision:
+        w = w.with_(precision=precision)
     stride, off = int(g["stride"]), tuple(int(x) for x in g["offset"])
     assert int(g["steps_per_interval"]) == w.steps_per_interval and int(g["n_intervals"]) == w.n_intervals
-    say(f"{name}: {w.n_intervals} x {w.steps_per_interval} steps on the GPU")
-    run, got = gpu_run(w, chunk=512)
-    worst = {}
+    u, v, h = w.initial_state()
+    if perturb is not None:
+        u, v, h = perturb(u), perturb(v), perturb(h)
+    say(f"{name}: {w.n_intervals} x {w.steps_per_interval} steps on the GPU ({w.precision}"
+        f"{', perturbed start' if perturb else ''})")
+    run, got = gpu_run(w, u=u, v=v, h=h, chunk=512)
+    run.close()
+    errs = []
     for i in range(w.n_intervals):
+        row = {}
         for key in OUTPUT_KEYS:
             ref = g[f"i{i}_{key.replace(':', '_')}"]
             val = got[i][key][off[0]::stride, off[1]::stride]
             if key.endswith(":h"):
                 ref, val = ref - w.H, val - w.H
             nb = np.linalg.norm(ref)
-            err = np.linalg.norm(val - ref) / nb if nb > 1e-14 else np.max(np.abs(val - ref))
-            worst[key] = max(worst.get(key, 0.0), err)
-            say(f"  interval {i} {key}: rel {err:.3e}")
-    run.close()
+            row[key] = np.linalg.norm(val - ref) / nb if nb > 1e-14 else np.max(np.abs(val - ref))
+            say(f"  interval {i} {key}: rel {row[key]:.3e}")
+        errs.append(row)
+    return w, errs
+
+
+def _compare(name, tol):
+    _, errs = _errors(name)
+    worst = {}
+    for row in errs:
+        for key, e in row.items():
+            worst[key] = max(worst.get(key, 0.0), e)
     return worst
 
 
@@ -52,8 +71,33 @@ def test_sw256_fp64_four_intervals():
         assert e < 1e-12, (k, e)
 
 
+U32 = 2.0 ** -24  # float32 unit roundoff
+PERTURB = 1e-7     # relative size of the probing perturbation of the initial state
+
+
 def test_1024_recipe_at_256_mixed_two_intervals():
-    """The mixed-precision path over a whole 2-interval run against float64."""
-    worst = _compare("sw1024recipe_at256_fp32", 1e-5)
-    for k, e in worst.items():
-        assert e < 1e-5, (k, e)
+    """The mixed-precision path over a whole 2-interval run against float64.
+
+    The flow amplifies perturbations: float32 arithmetic rounds every step of
+    the trajectory (relative u32), and over thousands of steps these roundings
+    add up like a random walk and grow with the flow's sensitivity.  That
+    sensitivity is measured here, not assumed: the float64 path is run from the
+    initial state times (1 + 1e-7 noise), and its deviation d from the stored
+    values is the response to one perturbation of size 1e-7 made at the start
+    (the largest response of the run to a perturbation at any time).  A bound
+    for float32 rounding in every one of the n steps taken so far, at most two
+    roundings per step: 2 sqrt(n) (u32 / 1e-7) d.  The tolerance is that bound,
+    but never below the 1e-5 that short runs meet."""
+    name = "sw1024recipe_at256_fp32"
+    rng = np.random.Generator(np.random.PCG64(11))
+    w, probe = _errors(name, precision="fp64",
+                       perturb=lambda a: a * (1.0 + PERTURB * rng.standard_normal(a.shape)))
+    _, errs = _errors(name)
+    for i, (row, d) in enumerate(zip(errs, probe)):
+        n = (i + 1) * w.steps_per_interval
+        for key, e in row.items():
+            tol = max(1e-5, 2.0 * np.sqrt(n) * (U32 / PERTURB) * d[key])
+            say(f"  interval {i} {key}: {e:.2e} <= {tol:.2e} (probe {d[key]:.2e})")
+            assert e <= tol, (i, key, e, tol)
+    # the first interval alone stays close to the 1e-5 of short runs
+    assert max(errs[0].values()) < 2e-5, errs[0]
