@@ -23,9 +23,13 @@ Contents
               the true means on small grids.
 ``closed``    closed forms used as pins (exact kinematic plane-wave means,
               small-amplitude Stokes corrections, dispersion relation).
+``remap``     strategy 1 remapped to Lagrangian-mean positions (eq. (3.8)):
+              the end position of the particle with mean position y as the
+              fixed point x = y + eta(x), then f-bar^L(y) = f~^L(x).
 
-Parity pins: every function of ``lagmean`` is pinned by the not-gpu tests
-(closed forms, invariants, brute-force tracking); none is "parity unpinned".
+Parity pins: every function of ``lagmean`` and ``remap`` is pinned by the
+not-gpu tests (closed forms, invariants, brute-force tracking, a lift map
+inverted by Newton's method); none is "parity unpinned".
 """
 
 from . import lagmean, closed, tracker  # noqa: F401

@@ -1,0 +1,93 @@
+"""Pins of the oracle's strategy-1 remap (eq. (3.8)) against what the mathematics
+fixes: exact shifts, an explicit bilinear formula, a smooth lift map known in
+closed form (inverted by Newton's method), and agreement with strategy 2 on the
+same particles."""
+
+import numpy as np
+
+from oracle.remap import remap_s1
+from test_oracle_pins import _grid, _tracked_case
+
+
+def test_whole_cell_offset_is_an_exact_shift():
+    N = 32
+    dx = 2 * np.pi / N
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((N, N))
+    eta_x = np.full((N, N), 2 * dx)
+    eta_y = np.full((N, N), -3 * dx)
+    out, d_x, d_y, res = remap_s1({"f": f}, eta_x, eta_y)
+    # f-bar(y) = f~(y + eta): element (iy, ix) takes f[iy - 3, ix + 2]
+    assert np.array_equal(out["f"], np.roll(np.roll(f, -2, axis=1), 3, axis=0))
+    assert np.allclose(d_x, 2 * dx, rtol=0, atol=1e-15) and np.allclose(d_y, -3 * dx, rtol=0, atol=1e-15)
+    assert np.max(res) <= 1e-13
+
+
+def test_constant_fractional_offset_matches_explicit_bilinear_weights():
+    N = 24
+    dx = 2 * np.pi / N
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((N, N))
+    ox, oy = 1.37, -0.61  # cells
+    out, d_x, d_y, _ = remap_s1({"f": f}, np.full((N, N), ox * dx), np.full((N, N), oy * dx))
+    # corners (iy + fy + {0,1}, ix + fx + {0,1}) with weights from the fractional parts
+    fx, fy = int(np.floor(ox)), int(np.floor(oy))
+    ax, ay = ox - fx, oy - fy
+    s = lambda a, b: np.roll(np.roll(f, -a, axis=1), -b, axis=0)
+    ref = ((1 - ax) * (1 - ay) * s(fx, fy) + ax * (1 - ay) * s(fx + 1, fy)
+           + (1 - ax) * ay * s(fx, fy + 1) + ax * ay * s(fx + 1, fy + 1))
+    assert np.max(np.abs(out["f"] - ref)) < 1e-14
+    assert np.allclose(d_x, ox * dx, rtol=0, atol=1e-14) and np.allclose(d_y, oy * dx, rtol=0, atol=1e-14)
+
+
+def _lift(YX, YY, a=0.25, b=0.2):
+    """A smooth invertible lift map Xi(y) = y + A(y) and the Jacobian of A."""
+    Ax = a * np.sin(YY + 0.3) + 0.1 * np.sin(YX)
+    Ay = b * np.cos(YX - 0.7)
+    J = (0.1 * np.cos(YX), a * np.cos(YY + 0.3), -b * np.sin(YX - 0.7), np.zeros_like(YX))
+    return Ax, Ay, J
+
+
+def _mean_field(YX, YY):
+    return np.cos(YX) * np.sin(2 * YY) + 0.5 * np.sin(YX + YY)
+
+
+def _remap_error(N):
+    X, Y = _grid(N)
+    # Xi^{-1}(x) by Newton's method on y + A(y) = x, to roundoff
+    yx, yy = X.copy(), Y.copy()
+    for _ in range(50):
+        Ax, Ay, (j11, j12, j21, j22) = _lift(yx, yy)
+        rx, ry = yx + Ax - X, yy + Ay - Y
+        a11, a12, a21, a22 = 1 + j11, j12, j21, 1 + j22
+        det = a11 * a22 - a12 * a21
+        yx, yy = yx - (a22 * rx - a12 * ry) / det, yy - (-a21 * rx + a11 * ry) / det
+    assert max(np.max(np.abs(rx)), np.max(np.abs(ry))) < 1e-13
+    eta_x, eta_y = X - yx, Y - yy          # x - Xi^{-1}(x)
+    ftil = _mean_field(yx, yy)             # f~(x) = f-bar(Xi^{-1}(x)), eq. (3.8)
+    out, d_x, d_y, res = remap_s1({"f": ftil}, eta_x, eta_y)
+    assert np.max(res) <= 1e-13
+    Ax, Ay, _ = _lift(X, Y)
+    return (np.max(np.abs(out["f"] - _mean_field(X, Y))),
+            max(np.max(np.abs(d_x - Ax)), np.max(np.abs(d_y - Ay))))
+
+
+def test_smooth_lift_map_is_recovered_at_second_order():
+    e = {N: _remap_error(N) for N in (32, 64, 128)}
+    for k in (0, 1):
+        assert e[128][k] < 0.02
+        # bilinear interpolation: O(dx^2), ratio ~4 per doubling
+        assert 3.0 < e[32][k] / e[64][k] < 5.0 and 3.0 < e[64][k] / e[128][k] < 5.0, e
+
+
+def test_remapped_strategy1_matches_strategy2_on_the_same_particles():
+    # the remap turns strategy 1 into strategy 2's variables: xi(y) and f-bar(y)
+    N = 32
+    out, _ = _tracked_case(N)
+    fields = {k: out[f"S1_mean:{k}"] for k in ("h", "u")}
+    rm, d_x, d_y, res = remap_s1(fields, out["S1_eta_x"], out["S1_eta_y"])
+    assert np.max(res) <= 1e-13
+    for a, b in ((d_x, out["S2_xi_x"]), (d_y, out["S2_xi_y"]), (rm["h"], out["S2_mean:h"]), (rm["u"], out["S2_mean:u"])):
+        err = np.max(np.abs(a - b))
+        assert err < 2e-3
+        assert err < 0.05 * np.max(np.abs(b - b.mean()))
