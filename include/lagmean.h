@@ -140,13 +140,40 @@ typedef enum {
   LM_K_S1_MEAN = 3,   /* strategy 1: f~^L at end-of-interval positions (field) */
   LM_K_S1_ETA_X = 4,  /* strategy 1: eta_x = x - Xi^{-1}_x(x, tau+T)          */
   LM_K_S1_ETA_Y = 5,  /* strategy 1: eta_y                                  */
-  LM_K_EULER_MEAN = 6 /* Eulerian time mean (field)                         */
+  LM_K_EULER_MEAN = 6, /* Eulerian time mean (field)                        */
+  LM_K_S1_REMAP_MEAN = 7, /* strategy 1 remapped: f-bar^L at Lagrangian-mean
+                             positions (field), after lm_remap_s1             */
+  LM_K_S1_REMAP_XI_X = 8, /* strategy 1 remapped: Xi_x(y) - y, the end position
+                             minus the mean position, as xi_x of strategy 2   */
+  LM_K_S1_REMAP_XI_Y = 9  /* strategy 1 remapped: Xi_y(y) - y                 */
 } lm_kind;
 typedef enum { LM_FIELD_H = 0, LM_FIELD_ZETA = 1 } lm_field;
 
+/* Remap the strategy-1 outputs of the last closed interval to Lagrangian-mean
+   positions (section 3.1, eq. (3.8): f~^L(x) = f-bar^L(Xi^{-1}(x))).  For every
+   grid point y, taken as a mean position, the end position x of its particle
+   solves x - eta(x) = y (eta = x - Xi^{-1}(x) from strategy 1, bilinear between
+   grid values, as the gathers of section 4.2.1); then f-bar^L(y) = f~^L(x)
+   (bilinear) and the displacement Xi(y) - y = x - y.  Solved exactly per
+   end-position cell: the cell's corner mean positions span a bilinear patch,
+   and every grid point the patch covers is located by inverting the patch
+   (closed form, then two Newton steps); no iteration that could fail to
+   contract where mean positions cluster (the paper's caveat, section 5).  Where
+   the mean map folds (a point covered by several patches) the patch of the
+   lowest cell index iy N + ix is taken.  Patches spanning more than max_extent
+   grid cells in x or y are skipped; a point no patch covers gets NaN.
+   float64.  1 <= max_extent <= 64 (else LM_E_ARG); LM_E_STATE before the
+   first lm_end_interval or while the run belongs to a batch.  *residual (may be
+   null) receives the largest |p(s, t) - y| over all points in grid spacings
+   (inversion error; infinite if some point is not covered).  The results are
+   read with lm_read_mean kinds LM_K_S1_REMAP_*, until the next
+   lm_end_interval.  Uses the run's boundary staging buffer.  Synchronous. */
+lm_status lm_remap_s1(lm_run* run, int32_t max_extent, double* residual);
+
 /* Copy one output of the last closed interval (N x N float64) to out.
    field is ignored for the displacement kinds.  LM_E_STATE before the first
-   lm_end_interval.  Synchronous. */
+   lm_end_interval, and for the LM_K_S1_REMAP_* kinds before lm_remap_s1 of
+   that interval.  Synchronous. */
 lm_status lm_read_mean(lm_run* run, int32_t field, int32_t kind, double* out, int on_device);
 
 /* raw prognostic fields for lm_peek */

@@ -27,7 +27,8 @@ cell, which the workloads reach within one interval; the patch inversion has
 no such limit.  Where the mean map folds (a point covered by several patches)
 the patch of the lowest cell index (iy N + ix) is taken; a point covered by no
 patch (only possible through a cell whose patch spans more than max_extent
-cells, which is then skipped) gets NaN and an infinite residual.
+cells, or lies more than 1e7 cells away, which is then skipped) gets NaN and
+an infinite residual.
 """
 
 from __future__ import annotations
@@ -113,7 +114,8 @@ def remap_s1(fields: Dict[str, np.ndarray], eta_x: np.ndarray, eta_y: np.ndarray
     ys = np.stack([p00[1], p10[1], p01[1], p11[1]])
     lo_x, hi_x = np.ceil(xs.min(0) - EPS), np.floor(xs.max(0) + EPS)
     lo_y, hi_y = np.ceil(ys.min(0) - EPS), np.floor(ys.max(0) + EPS)
-    usable = (hi_x - lo_x <= max_extent) & (hi_y - lo_y <= max_extent)
+    usable = ((hi_x - lo_x <= max_extent) & (hi_y - lo_y <= max_extent)
+              & (np.abs(lo_x) < 1e7) & (np.abs(hi_x) < 1e7) & (np.abs(lo_y) < 1e7) & (np.abs(hi_y) < 1e7))
     ext_x = int(np.max(np.where(usable, hi_x - lo_x, 0)))
     ext_y = int(np.max(np.where(usable, hi_y - lo_y, 0)))
     cell = IY * N + IX

@@ -59,7 +59,7 @@ lm_status check_cfg(const lm_config* cfg) {
 
 struct lm_run : lm::RunView {
   lm_config cfg;
-  bool has_state, in_interval, has_mean;
+  bool has_state, in_interval, has_mean, has_remap;
   double T;
   lm_batch* batch;  // the batch this run belongs to, if any
 };
@@ -169,7 +169,7 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
   r->fp32 = cfg->precision == LM_FP32_MIXED;
   r->L = lm::make_layout(r->d, r->fp32);
   r->n = r->n_tau = 0;
-  r->has_state = r->in_interval = r->has_mean = false;
+  r->has_state = r->in_interval = r->has_mean = r->has_remap = false;
   r->T = 0.0;
   r->ys_cur = 0;
   r->slab = nullptr;
@@ -311,6 +311,7 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
   const size_t nn = (size_t)r->d.N * r->d.N, rf = r->d.rowfield_elems();
   cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
   double* out = (double*)r->at(r->L.out);
+  r->has_remap = false;  // a remap describes the previous outputs
   // accumulators in output order: (gbar_h, gbar_z), (xi_x, xi_y), (gtil_h, gtil_z), (P_x, P_y), (E_h, E_z)
   static const int order[10] = {LM_P_GBAR_H, LM_P_GBAR_ZETA, LM_P_XI_X, LM_P_XI_Y, LM_P_GTIL_H,
                                 LM_P_GTIL_ZETA, LM_P_P_X, LM_P_P_Y, LM_P_E_H, LM_P_E_ZETA};
@@ -353,6 +354,32 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
   return LM_OK;
 }
 
+lm_status lm_remap_s1(lm_run* r, int32_t max_extent, double* residual) {
+  if (!r) return fail(LM_E_ARG, "null run");
+  if (max_extent < 1 || max_extent > 64) return fail(LM_E_ARG, "max_extent must be in 1..64");
+  if (!r->has_mean) return fail(LM_E_STATE, "no closed interval");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
+  const size_t nn = (size_t)r->d.N * r->d.N;
+  double* out = (double*)r->at(r->L.out);
+  unsigned long long* bits = (unsigned long long*)r->at(r->L.resid);
+  // the boundary staging buffer (3 N^2 float64) holds the claims (N^2 uint32)
+  unsigned* best = (unsigned*)r->at(r->L.phys);
+  HIP_TRY(hipMemsetAsync(bits, 0, sizeof(unsigned long long), r->stream));
+  // inputs: S1 means (planes 4, 5) and eta (6, 7); outputs after the Eulerian planes
+  lm::launch_remap_s1(*r, out + 4 * nn, out + 5 * nn, out + 6 * nn, out + 7 * nn, out + lm::OUT_REMAP * nn, best,
+                      max_extent, bits);
+  lm_status s;
+  if ((s = check_launch()) != LM_OK) return s;
+  unsigned long long hb = 0;
+  HIP_TRY(hipMemcpyAsync(&hb, bits, sizeof(hb), hipMemcpyDeviceToHost, r->stream));
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  double res;
+  memcpy(&res, &hb, sizeof(res));
+  r->has_remap = true;
+  if (residual) *residual = res;
+  return LM_OK;
+}
+
 lm_status lm_read_mean(lm_run* r, int32_t field, int32_t kind, double* out_, int on_device) {
   if (!r || !out_) return fail(LM_E_ARG, "null argument");
   if (!r->has_mean) return fail(LM_E_STATE, "no closed interval");
@@ -366,8 +393,12 @@ lm_status lm_read_mean(lm_run* r, int32_t field, int32_t kind, double* out_, int
     case LM_K_S1_ETA_X: idx = 6; break;
     case LM_K_S1_ETA_Y: idx = 7; break;
     case LM_K_EULER_MEAN: idx = 8 + field; break;
+    case LM_K_S1_REMAP_MEAN: idx = lm::OUT_REMAP + field; break;
+    case LM_K_S1_REMAP_XI_X: idx = lm::OUT_REMAP + 2; break;
+    case LM_K_S1_REMAP_XI_Y: idx = lm::OUT_REMAP + 3; break;
     default: return fail(LM_E_ARG, "unknown kind");
   }
+  if (idx >= lm::OUT_REMAP && !r->has_remap) return fail(LM_E_STATE, "no strategy-1 remap of the last interval");
   const size_t nn = (size_t)r->d.N * r->d.N;
   lm_status s = copy_out(r, out_, (double*)r->at(r->L.out) + idx * nn, on_device);
   if (s != LM_OK) return s;

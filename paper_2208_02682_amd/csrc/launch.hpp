@@ -18,6 +18,9 @@ template <int N> void launch_io_col_forward(RunView& r, const IoColFwd& J, int c
 template <int N> void launch_io_col_inverse(RunView& r, const IoColInv& J, int count);
 template <int N> void launch_io_row_inverse(RunView& r, const IoRowInv& J, int count);
 void launch_nonfinite(RunView& r, const double* a, size_t n, int* flag);
+// strategy-1 remap of the interval outputs (float64, N x N planes)
+void launch_remap_s1(RunView& r, const double* fh, const double* fz, const double* ex, const double* ey,
+                     double* out, unsigned* best, int max_extent, unsigned long long* resid_bits);
 
 #define LM_DISPATCH_N_RET(n, out, FN, ...)       \
   switch (n) {                                    \

@@ -18,9 +18,15 @@ namespace lm {
 constexpr size_t SLAB_ALIGN = 256;
 inline size_t slab_up(size_t x) { return (x + SLAB_ALIGN - 1) / SLAB_ALIGN * SLAB_ALIGN; }
 
+// float64 output planes of a closed interval: S2 mean h, zeta, xi_x, xi_y;
+// S1 mean h, zeta, eta_x, eta_y; Eulerian h, zeta; the strategy-1 remap
+// (mean h, zeta at mean positions, displacement x, y)
+constexpr int NOUT = 14;
+constexpr int OUT_REMAP = 10;
+
 // byte offsets of every buffer inside the slab
 struct Layout {
-  size_t Yr, Yd, Ar, Ad, Ys0, Ys1, IC, RS, uvhz, tw64, twT, out, phys, ioC, flag, total;
+  size_t Yr, Yd, Ar, Ad, Ys0, Ys1, IC, RS, uvhz, tw64, twT, out, phys, ioC, flag, resid, total;
 };
 
 inline Layout make_layout(const Dims& d, bool fp32) {
@@ -45,10 +51,11 @@ inline Layout make_layout(const Dims& d, bool fp32) {
   L.uvhz = take(nn * 4 * (fp32 ? sizeof(float) : sizeof(double)));
   L.tw64 = take((size_t)d.N * cD);
   L.twT = take((size_t)d.N * cT);
-  L.out = take(10 * nn * sizeof(double));
+  L.out = take(NOUT * nn * sizeof(double));
   L.phys = take(3 * nn * sizeof(double));
   L.ioC = take(10 * rf * cD);
   L.flag = take(sizeof(int));
+  L.resid = take(sizeof(unsigned long long));
   L.total = o;
   return L;
 }

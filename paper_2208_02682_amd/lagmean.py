@@ -21,7 +21,8 @@ LM_OK = 0
 STATUS = {0: "LM_OK", -1: "LM_E_ARG", -2: "LM_E_STATE", -3: "LM_E_OOM", -4: "LM_E_HIP",
           -5: "LM_E_NONFINITE", -6: "LM_E_UNSUPPORTED", -7: "LM_E_BUDGET"}
 LM_FP64, LM_FP32_MIXED = 0, 1
-LM_K_S2_MEAN, LM_K_S2_XI_X, LM_K_S2_XI_Y, LM_K_S1_MEAN, LM_K_S1_ETA_X, LM_K_S1_ETA_Y, LM_K_EULER_MEAN = range(7)
+(LM_K_S2_MEAN, LM_K_S2_XI_X, LM_K_S2_XI_Y, LM_K_S1_MEAN, LM_K_S1_ETA_X, LM_K_S1_ETA_Y, LM_K_EULER_MEAN,
+ LM_K_S1_REMAP_MEAN, LM_K_S1_REMAP_XI_X, LM_K_S1_REMAP_XI_Y) = range(10)
 LM_FIELD_H, LM_FIELD_ZETA = 0, 1
 PEEK = {"u": 0, "v": 1, "h": 2, "gbar:h": 3, "gbar:zeta": 4, "gtil:h": 5, "gtil:zeta": 6,
         "E:h": 7, "E:zeta": 8, "xi_x": 9, "xi_y": 10, "P_x": 11, "P_y": 12}
@@ -32,6 +33,11 @@ OUTPUTS = {
     "S1_mean:h": (LM_FIELD_H, LM_K_S1_MEAN), "S1_mean:zeta": (LM_FIELD_ZETA, LM_K_S1_MEAN),
     "S1_eta_x": (0, LM_K_S1_ETA_X), "S1_eta_y": (0, LM_K_S1_ETA_Y),
     "E_mean:h": (LM_FIELD_H, LM_K_EULER_MEAN), "E_mean:zeta": (LM_FIELD_ZETA, LM_K_EULER_MEAN),
+}
+# outputs of lm_remap_s1 (strategy 1 at Lagrangian-mean positions)
+REMAP_OUTPUTS = {
+    "S1R_mean:h": (LM_FIELD_H, LM_K_S1_REMAP_MEAN), "S1R_mean:zeta": (LM_FIELD_ZETA, LM_K_S1_REMAP_MEAN),
+    "S1R_xi_x": (0, LM_K_S1_REMAP_XI_X), "S1R_xi_y": (0, LM_K_S1_REMAP_XI_Y),
 }
 
 
@@ -71,6 +77,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_step_profiled": [P, ctypes.c_int32, D],
         "lm_end_interval": [P, D],
         "lm_read_mean": [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int],
+        "lm_remap_s1": [P, ctypes.c_int32, D],
         "lm_peek": [P, ctypes.c_int32, P, ctypes.c_int],
         "lm_counters": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "lm_destroy": [P],
@@ -199,6 +206,16 @@ class Run:
 
     def outputs(self) -> Dict[str, np.ndarray]:
         return {name: self.read_mean(fk[0], fk[1]) for name, fk in OUTPUTS.items()}
+
+    def remap_s1(self, max_extent: int = 64) -> float:
+        """Strategy 1 at Lagrangian-mean positions (lm_remap_s1); returns the
+        largest inversion residual in grid spacings (inf if a point is not covered)."""
+        res = ctypes.c_double(0.0)
+        _check(self.lib.lm_remap_s1(self.h, int(max_extent), ctypes.byref(res)))
+        return res.value
+
+    def remap_outputs(self) -> Dict[str, np.ndarray]:
+        return {name: self.read_mean(fk[0], fk[1]) for name, fk in REMAP_OUTPUTS.items()}
 
     def peek(self, which: str):
         out = np.empty((self.N, self.N))
