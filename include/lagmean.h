@@ -68,8 +68,11 @@ typedef enum { LM_FP64 = 0, LM_FP32_MIXED = 1 } lm_precision;
 #define LM_S1 1u
 #define LM_S2 2u
 #define LM_EULER 4u
-/* gather interpolation */
-#define LM_INTERP_BILINEAR 0
+/* gather interpolation of strategy 2 (u and the averaged fields at x + xi) */
+#define LM_INTERP_BILINEAR 0 /* periodic bilinear, as section 4.2.1 */
+#define LM_INTERP_CUBIC 1    /* periodic tensor-product cubic (4-point Lagrange, 4 x 4
+                                points; the paper compares linear and cubic
+                                interpolation for strategy 1, section 4.1) */
 /* driver of u, v, h */
 #define LM_DYNAMIC 0
 
@@ -84,7 +87,7 @@ typedef struct {
   double nu8;          /* eighth-order hyperviscosity on u, v, h (>= 0) */
   uint32_t avg_fields; /* must be LM_F_H | LM_F_ZETA (or 0 for the default) */
   uint32_t strategies; /* must be LM_S1 | LM_S2 | LM_EULER (or 0 for the default) */
-  int32_t interp;      /* LM_INTERP_BILINEAR */
+  int32_t interp;      /* LM_INTERP_BILINEAR or LM_INTERP_CUBIC */
   int32_t mode;        /* LM_DYNAMIC */
 } lm_config;
 

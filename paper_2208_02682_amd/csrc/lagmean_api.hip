@@ -50,7 +50,8 @@ lm_status check_cfg(const lm_config* cfg) {
     return fail(LM_E_UNSUPPORTED, "averaged fields are h and zeta");
   if (cfg->strategies != 0 && cfg->strategies != (LM_S1 | LM_S2 | LM_EULER))
     return fail(LM_E_UNSUPPORTED, "all of strategy 1, strategy 2 and the Eulerian mean are integrated");
-  if (cfg->interp != LM_INTERP_BILINEAR) return fail(LM_E_UNSUPPORTED, "bilinear interpolation only");
+  if (cfg->interp != LM_INTERP_BILINEAR && cfg->interp != LM_INTERP_CUBIC)
+    return fail(LM_E_UNSUPPORTED, "interp must be LM_INTERP_BILINEAR or LM_INTERP_CUBIC");
   if (cfg->mode != LM_DYNAMIC) return fail(LM_E_UNSUPPORTED, "dynamic mode only");
   return LM_OK;
 }
@@ -72,6 +73,7 @@ struct lm_batch {
   struct Group {
     int N;
     bool fp32;
+    bool cubic;
     void* d_desc = nullptr;  // device array of RunDesc<T>
     size_t cap = 0;          // bytes
     hipStream_t fork = nullptr;
@@ -167,6 +169,7 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
   r->ph = lm::Phys{cfg->f, cfg->g, cfg->H, cfg->dt, cfg->nu8};
   r->stream = (hipStream_t)hip_stream;
   r->fp32 = cfg->precision == LM_FP32_MIXED;
+  r->cubic = cfg->interp == LM_INTERP_CUBIC;
   r->L = lm::make_layout(r->d, r->fp32);
   r->n = r->n_tau = 0;
   r->has_state = r->in_interval = r->has_mean = r->has_remap = false;
@@ -453,12 +456,13 @@ lm_status lm_destroy(lm_run* r) {
 // ---------------------------------------------------------------------------
 namespace {
 
-lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32) {
+lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32, bool cubic) {
   for (auto& g : b->groups)
-    if (g.N == N && g.fp32 == fp32) return &g;
+    if (g.N == N && g.fp32 == fp32 && g.cubic == cubic) return &g;
   lm_batch::Group g;
   g.N = N;
   g.fp32 = fp32;
+  g.cubic = cubic;
   if (hipStreamCreateWithFlags(&g.fork, hipStreamNonBlocking) != hipSuccess) return nullptr;
   if (hipEventCreateWithFlags(&g.join, hipEventDisableTiming) != hipSuccess) return nullptr;
   b->groups.push_back(g);
@@ -466,11 +470,12 @@ lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32) {
 }
 
 template <typename T>
-std::vector<char> group_descs(lm_batch* b, int N, bool fp32, const std::vector<int>& active, int* count) {
+std::vector<char> group_descs(lm_batch* b, int N, bool fp32, bool cubic, const std::vector<int>& active,
+                              int* count) {
   std::vector<lm::RunDesc<T>> d;
   for (int i : active) {
     lm_run* r = b->members[i].run;
-    if (r->d.N == N && r->fp32 == fp32) d.push_back(lm::run_desc<T>(*r, b->d_counters + i));
+    if (r->d.N == N && r->fp32 == fp32 && r->cubic == cubic) d.push_back(lm::run_desc<T>(*r, b->d_counters + i));
   }
   *count = (int)d.size();
   std::vector<char> bytes(d.size() * sizeof(lm::RunDesc<T>));
@@ -499,13 +504,13 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
   std::vector<Launch> launches;
   for (int i : active) {
     lm_run* r = b->members[i].run;
-    lm_batch::Group* g = batch_group(b, r->d.N, r->fp32);
+    lm_batch::Group* g = batch_group(b, r->d.N, r->fp32, r->cubic);
     if (!g) return fail(LM_E_HIP, "batch: stream or event creation failed");
   }
   for (auto& g : b->groups) {
     int count = 0;
-    std::vector<char> bytes = g.fp32 ? group_descs<float>(b, g.N, true, active, &count)
-                                     : group_descs<double>(b, g.N, false, active, &count);
+    std::vector<char> bytes = g.fp32 ? group_descs<float>(b, g.N, true, g.cubic, active, &count)
+                                     : group_descs<double>(b, g.N, false, g.cubic, active, &count);
     if (count == 0) continue;
     if (bytes.size() > g.cap) {
       if (g.d_desc) (void)hipFree(g.d_desc);
@@ -523,7 +528,7 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
   for (auto& l : launches) {
     if (e == hipSuccess) e = hipStreamWaitEvent(l.g->fork, b->fork_ev, 0);
     if (e == hipSuccess) {
-      LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32);
+      LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32, l.g->cubic);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(l.g->join, l.g->fork);

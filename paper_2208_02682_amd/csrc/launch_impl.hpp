@@ -40,6 +40,14 @@ void launch_columns_t(RunView& r, int stage) {
 }
 
 template <typename T, int N>
+void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
+  if (r.cubic)
+    hipLaunchKernelGGL((k_rows_rhs<T, N, true>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
+  else
+    hipLaunchKernelGGL((k_rows_rhs<T, N, false>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
+}
+
+template <typename T, int N>
 void launch_steps_t(RunView& r, int nsteps) {
   const StepPtrs<T> P = step_ptrs<T>(r);
   static const double c[4] = {0.0, 0.5, 0.5, 1.0};
@@ -48,7 +56,7 @@ void launch_steps_t(RunView& r, int nsteps) {
       // time since the interval start, from integers
       const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
       hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d);
-      hipLaunchKernelGGL((k_rows_rhs<T, N>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
+      launch_rows_rhs<T, N>(r, P, sval);
       launch_columns_t<T, N>(r, stage);
     }
     r.n += 1;
@@ -85,7 +93,7 @@ hipError_t launch_steps_profiled_t(RunView& r, int nsteps, double* ms) {
       (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
       (void)hipEventRecord(ev[e++], r.stream);
-      hipLaunchKernelGGL((k_rows_rhs<T, N>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
+      launch_rows_rhs<T, N>(r, P, sval);
       (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
       (void)hipEventRecord(ev[e++], r.stream);
@@ -114,7 +122,7 @@ hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms) {
 // one RK4 step of every run of one (N, precision) group: blockIdx.z selects
 // the run's descriptor
 template <typename T, int N>
-void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns) {
+void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool cubic) {
   const Dims d = Dims::make(N);
   for (int stage = 0; stage < 4; ++stage) {
     dim3 g1 = row_grid<N>(1);
@@ -122,7 +130,8 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns) {
     hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, dim3(64 * ROW_WAVES), 0, st, desc);
     dim3 g2 = row_grid<N>(NRT);
     g2.z = nruns;
-    hipLaunchKernelGGL((k_rows_rhs_b<T, N>), g2, dim3(64 * ROW_WAVES), 0, st, desc, stage);
+    if (cubic) hipLaunchKernelGGL((k_rows_rhs_b<T, N, true>), g2, dim3(64 * ROW_WAVES), 0, st, desc, stage);
+    else hipLaunchKernelGGL((k_rows_rhs_b<T, N, false>), g2, dim3(64 * ROW_WAVES), 0, st, desc, stage);
     dim3 g3 = col_grid<N>(d, NCG);
     g3.z = nruns;
     hipLaunchKernelGGL((k_columns_b<T, N>), g3, col_block<N>(), 0, st, desc, stage);
@@ -130,9 +139,9 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns) {
 }
 
 template <int N>
-void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32) {
-  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns);
-  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns);
+void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic) {
+  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns, cubic);
+  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns, cubic);
 }
 
 template <int N>
@@ -173,7 +182,7 @@ void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
 #define LM_INSTANTIATE(N)                                                                \
   namespace lm {                                                                         \
   template void launch_steps<N>(RunView&, int);                                          \
-  template void launch_batch_step<N>(hipStream_t, const void*, int, bool);               \
+  template void launch_batch_step<N>(hipStream_t, const void*, int, bool, bool);         \
   template hipError_t launch_steps_profiled<N>(RunView&, int, double*);                  \
   template void launch_prologue<N>(RunView&);                                            \
   template void launch_io_row_forward<N>(RunView&, const IoRowFwd&, int);                \

@@ -65,6 +65,7 @@ struct RunView {
   Phys ph;
   hipStream_t stream;
   bool fp32;
+  bool cubic;        // cubic strategy-2 gathers (else bilinear)
   Layout L;
   char* slab;
   int64_t n, n_tau;  // steps since set_state; step index at the interval start

@@ -190,6 +190,51 @@ __device__ __forceinline__ cplx<T> gather2(const P4<T>* __restrict__ F, int x, i
           w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y};
 }
 
+// periodic tensor-product cubic (4-point Lagrange) interpolation at x + xi of
+// one pair of the interleaved physical fields, PAIR as in gather2: with
+// o = xi / dx, i0 = floor(o), a = o - i0, the nodes i0-1 .. i0+2 carry
+// -a(a-1)(a-2)/6, (a+1)(a-1)(a-2)/2, -(a+1)a(a-2)/2, (a+1)a(a-1)/6
+template <typename T, int N, int PAIR>
+__device__ __forceinline__ cplx<T> gather2_cubic(const P4<T>* __restrict__ F, int x, int y, T xix, T xiy) {
+  const T scl = T(double(N) / 6.283185307179586476925286766559);
+  T ox = xix * scl, oy = xiy * scl;
+  T fx = floor(ox), fy = floor(oy);
+  fx = fmin(fmax(fx, T(-N)), T(N));
+  fy = fmin(fmax(fy, T(-N)), T(N));
+  const T ax = ox - fx, ay = oy - fy;
+  const T wx[4] = {-ax * (ax - T(1)) * (ax - T(2)) / T(6), (ax + T(1)) * (ax - T(1)) * (ax - T(2)) / T(2),
+                   -(ax + T(1)) * ax * (ax - T(2)) / T(2), (ax + T(1)) * ax * (ax - T(1)) / T(6)};
+  const T wy[4] = {-ay * (ay - T(1)) * (ay - T(2)) / T(6), (ay + T(1)) * (ay - T(1)) * (ay - T(2)) / T(2),
+                   -(ay + T(1)) * ay * (ay - T(2)) / T(2), (ay + T(1)) * ay * (ay - T(1)) / T(6)};
+  const int bx = wrap2N<N>(x + int(fx)), by = wrap2N<N>(y + int(fy));
+  const char* F2 = reinterpret_cast<const char*>(F) + PAIR * sizeof(cplx<T>);
+  constexpr unsigned PT = sizeof(P4<T>), ROW = N * sizeof(P4<T>);
+  unsigned col[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int c = bx + i - 1;
+    c = c < 0 ? c + N : (c >= N ? c - N : c);
+    col[i] = unsigned(c) * PT;
+  }
+  cplx<T> out = {T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int r = by + j - 1;
+    r = r < 0 ? r + N : (r >= N ? r - N : r);
+    const unsigned ro = unsigned(r) * ROW;
+    cplx<T> row = {T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const cplx<T> f = *reinterpret_cast<const cplx<T>*>(F2 + (ro + col[i]));
+      row.x += wx[i] * f.x;
+      row.y += wx[i] * f.y;
+    }
+    out.x += wy[j] * row.x;
+    out.y += wy[j] * row.y;
+  }
+  return out;
+}
+
 // periodic bilinear interpolation of the interleaved physical fields at x + xi
 template <typename T, int N>
 __device__ __forceinline__ P4<T> gather4(const P4<T>* __restrict__ F, int x, int y, T xix, T xiy) {
@@ -289,7 +334,7 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims
 //   RT_GT  strategy 1, g-tilde of eta and zeta (eq. (4.1))
 //   RT_P   strategy 1, both P components (eq. (3.9) in P form)
 // The two strategy-2 tasks each transform xi and gather at x + xi.
-template <typename T, int N>
+template <typename T, int N, bool CUB>
 __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
                                               int task, cplx<T>* lds) {
   using G = RowGeo<N>;
@@ -326,7 +371,19 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
     constexpr int GG = 4;
     static_assert(E % GG == 0, "gather groups");
     const bool xi_task = (task == RT_XI);
-    if (xi_task) {
+    if constexpr (CUB) {
+      // cubic gathers: 16 corners per point, one point in flight at a time
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (xi_task) {
+          const cplx<T> g = gather2_cubic<T, N, 0>(F, t + NT * e, y, a[e].x, a[e].y);
+          a[e] = {g.x - w[e].x, g.y - w[e].y};
+        } else {
+          a[e] = gather2_cubic<T, N, 1>(F, t + NT * e, y, a[e].x, a[e].y);
+        }
+        sched_fence();
+      }
+    } else if (xi_task) {
 #pragma unroll
       for (int e0 = 0; e0 < E; e0 += GG) {
 #pragma unroll
@@ -386,12 +443,13 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
   }
 }
 
-template <typename T, int N>
+// CUB: cubic instead of bilinear strategy-2 gathers
+template <typename T, int N, bool CUB>
 __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, task, z;
   xcd_split(gridDim.x, gridDim.y, rowblock, task, z);  // grid = (row blocks, tasks)
-  rows_rhs_body<T, N>(P, d, s, rowblock, task, lds);
+  rows_rhs_body<T, N, CUB>(P, d, s, rowblock, task, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -668,7 +726,7 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn_b(const RunDesc<T>*
   rows_dyn_body<T, N>(runs[z].P, Dims::make(N), rowblock, lds);
 }
 
-template <typename T, int N>
+template <typename T, int N, bool CUB>
 __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>* __restrict__ runs, int stage) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, task, z;
@@ -677,7 +735,7 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>*
   // time since the interval start, from integers (as the single-run path)
   const double c = (stage == 0) ? 0.0 : ((stage == 3) ? 1.0 : 0.5);
   const double s = (double(*R.counter) + c) * R.ph.dt;
-  rows_rhs_body<T, N>(R.P, Dims::make(N), s, rowblock, task, lds);
+  rows_rhs_body<T, N, CUB>(R.P, Dims::make(N), s, rowblock, task, lds);
 }
 
 // stage parity selects the stage-value buffers: between steps the current

@@ -106,11 +106,14 @@ def _check(status: int) -> None:
         raise LagMeanError(status, msg)
 
 
+LM_INTERP = {"bilinear": 0, "cubic": 1}
+
+
 def make_config(n: int, *, precision: str = "fp64", f: float = 1.0, g: float = 1.0, H: float = 1.0,
-                dt: float, nu8: float = 0.0) -> Config:
+                dt: float, nu8: float = 0.0, interp: str = "bilinear") -> Config:
     prec = {"fp64": LM_FP64, "fp32": LM_FP32_MIXED}[precision]
     return Config(n=n, precision=prec, f=f, g=g, H=H, dt=dt, nu8=nu8, avg_fields=0, strategies=0,
-                  interp=0, mode=0)
+                  interp=LM_INTERP[interp], mode=0)
 
 
 def footprint(cfg: Config) -> int:

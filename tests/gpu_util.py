@@ -24,21 +24,21 @@ def compare_value(key: str, a: np.ndarray, b: np.ndarray, H: float = 1.0) -> flo
     return relative_l2(a, b)
 
 
-def oracle_run(w, steps_per_interval=None, n_intervals=None, u=None, v=None, h=None):
+def oracle_run(w, steps_per_interval=None, n_intervals=None, u=None, v=None, h=None, interp="bilinear"):
     if u is None:
         u, v, h = w.initial_state()
-    p = Params(N=w.N, dt=w.dt, f=w.f, g=w.g, H=w.H, nu8=w.nu8)
+    p = Params(N=w.N, dt=w.dt, f=w.f, g=w.g, H=w.H, nu8=w.nu8, interp=interp)
     r = OracleRun(p, u, v, h)
     spi = steps_per_interval or w.steps_per_interval
     ni = n_intervals or w.n_intervals
     return r, r.run_intervals(spi, ni)
 
 
-def gpu_run(w, steps_per_interval=None, n_intervals=None, u=None, v=None, h=None, chunk=None):
+def gpu_run(w, steps_per_interval=None, n_intervals=None, u=None, v=None, h=None, chunk=None, interp="bilinear"):
     from paper_2208_02682_amd import Run, make_config
     if u is None:
         u, v, h = w.initial_state()
-    cfg = make_config(w.N, precision=w.precision, f=w.f, g=w.g, H=w.H, dt=w.dt, nu8=w.nu8)
+    cfg = make_config(w.N, precision=w.precision, f=w.f, g=w.g, H=w.H, dt=w.dt, nu8=w.nu8, interp=interp)
     run = Run(cfg)
     run.set_state(u, v, h)
     spi = steps_per_interval or w.steps_per_interval
