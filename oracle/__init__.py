@@ -23,11 +23,14 @@ Contents
               the true means on small grids.
 ``closed``    closed forms used as pins (exact kinematic plane-wave means,
               small-amplitude Stokes corrections, dispersion relation).
+``euler2d``   two-dimensional incompressible inviscid flow (section 4.1) with
+              strategy 1 pseudospectral (eqs. (4.1), (3.9)) and
+              semi-Lagrangian (appendix B, eqs. (B.2), (B.4), (B.5)).
 ``remap``     strategy 1 remapped to Lagrangian-mean positions (eq. (3.8)):
               the end position of the particle with mean position y as the
               fixed point x = y + eta(x), then f-bar^L(y) = f~^L(x).
 
-Parity pins: every function of ``lagmean`` and ``remap`` is pinned by the
+Parity pins: every function of ``lagmean``, ``remap`` and ``euler2d`` is pinned by the
 not-gpu tests (closed forms, invariants, brute-force tracking, a lift map
 inverted by Newton's method); none is "parity unpinned".
 """
