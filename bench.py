@@ -15,14 +15,17 @@ Prints one JSON line with the driver's keys plus
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Two more modes print one JSON line each:
+Three more modes print one JSON line each:
   --mode batch : 64 independent runs of uneven N (128..512, float32 transforms)
                  advanced together by one lm_batch, against the same runs one
                  after another alone and as plain float64 runs;
   --mode serve : Poisson arrivals of averaging requests (N in 128..1024) served
                  with admission by HBM footprint and continuous batching: p50/p99
                  latency from arrival to means on the host, at the offered rate
-                 and at a sustainable rate (offered load 0.7 of the measured capacity).
+                 and at a sustainable rate (offered load 0.7 of the measured capacity);
+  --mode euler : the two-dimensional incompressible test (two vortices, 128^2,
+                 T = 25) with strategy 1 pseudospectral and semi-Lagrangian, and
+                 the semi-Lagrangian kernel at 1024^2 against HBM.
 """
 
 from __future__ import annotations
@@ -315,6 +318,61 @@ def bench_serve(a) -> dict:
     return rec
 
 
+def bench_euler(a) -> dict:
+    """The two-dimensional incompressible test of section 4.1 (128^2, dt 0.005,
+    T = 25) with strategy 1 pseudospectral and semi-Lagrangian, plus the
+    semi-Lagrangian kernel (FFT-free, gather-bound) at 1024^2 against HBM."""
+    import numpy as np
+    import torch
+    from paper_2208_02682_amd import Euler2D
+    from synth.euler import EULER_TWO_VORTEX as W, two_vortex_vorticity
+
+    torch.cuda.set_device(0)
+    z0 = W.initial_vorticity()
+    runs = {}
+    for interp in ("bilinear", "cubic"):
+        with Euler2D(W.N, W.dt, interp=interp) as e:
+            e.set_vorticity(z0)
+            e.begin_interval()
+            e.step(10)                       # warm-up inside the interval
+            e.set_vorticity(z0)
+            e.begin_interval()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e.step(W.steps)
+            e.end_interval()
+            el = time.perf_counter() - t0
+            out = e.outputs()
+        rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+        runs[interp] = {"seconds": el, "grid_point_steps_per_s": W.N * W.N * W.steps / el,
+                        "material_conservation_rel_l2": {"pseudospectral": rel(out["PS_mean"], out["zeta"]),
+                                                         "semi_lagrangian": rel(out["SL_mean"], out["zeta"])}}
+        print(f"euler: {interp} interval in {el:.2f} s", file=sys.stderr, flush=True)
+    # the semi-Lagrangian kernel at 1024^2: 3 inputs (u, v, zeta_{n+1}), 4 gathered
+    # fields each read once, 4 outputs, float64
+    N = 1024
+    sl = {}
+    for interp in ("bilinear", "cubic"):
+        with Euler2D(N, 0.0025, interp=interp) as e:
+            e.set_vorticity(two_vortex_vorticity(N))
+            e.begin_interval()
+            e.step(5)
+            ms_step, ms_sl = e.step_profiled(100)
+        ab = 11 * 8 * N * N
+        sl[interp] = {"avg_ms": ms_sl, "alg_bytes": ab, "GBps": ab / (ms_sl * 1e-3) / 1e9,
+                      "frac": ab / (ms_sl * 1e-3) / (HBM_PEAK_GBS * 1e9), "step_ms": ms_step}
+    return {"metric": "grid-pt steps/s, 2-D incompressible flow with strategy 1 pseudospectral and semi-Lagrangian",
+            "value": runs["cubic"]["grid_point_steps_per_s"], "unit": "grid-pt steps/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{W.name}: two Gaussian vortices (eq. (4.3)), N = {W.N}, dt = {W.dt}, "
+                                   f"T = {W.T} ({W.steps} Heun steps), one interval; value = cubic gathers",
+                       "N": W.N, "steps": W.steps},
+            "runs": runs,
+            "roofline": {"bound": "hbm", "kernel": "k_e2d_sl (1024^2, cubic)", "achieved": sl["cubic"]["GBps"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sl["cubic"]["frac"], "traffic": None},
+            "sl_kernel_1024": sl}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,7 +383,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed replay (roofline fields become null)")
-    ap.add_argument("--mode", choices=("step", "batch", "serve"), default="step")
+    ap.add_argument("--mode", choices=("step", "batch", "serve", "euler"), default="step")
     ap.add_argument("--batch-runs", type=int, default=64)
     ap.add_argument("--tick-steps", type=int, default=32, help="batch/serve: steps per lm_batch_step call")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
@@ -345,8 +403,8 @@ def main(argv=None) -> int:
               f"--gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
 
-    if a.mode in ("batch", "serve"):
-        rec = bench_batch(a) if a.mode == "batch" else bench_serve(a)
+    if a.mode in ("batch", "serve", "euler"):
+        rec = {"batch": bench_batch, "serve": bench_serve, "euler": bench_euler}[a.mode](a)
         print(json.dumps(rec), flush=True)
         return 0
     import numpy as np

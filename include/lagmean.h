@@ -235,6 +235,62 @@ lm_status lm_batch_remaining(lm_batch* b, const lm_run* run, int32_t* remaining)
 lm_status lm_batch_destroy(lm_batch* b);
 
 /* Text of a status code (static storage). */
+/* ---------------------------------------------------------------------------
+ * Two-dimensional incompressible inviscid flow with strategy 1 in two
+ * discretisations: the test of the paper's section 4.1 (material conservation
+ * of vorticity, eq. (4.2): zeta~^L(x, tau) = zeta(x, tau + T)) and appendix B.
+ *   dynamics: dzeta/dt + (u + U0) . grad zeta = 0, u = (-dpsi/dy, dpsi/dx),
+ *     lap psi = zeta; pseudospectral with the 2/3-rule square mask, Heun's
+ *     method (as section 4.1), no dissipation;
+ *   strategy 1 pseudospectral, in the same Heun stages: g~ = (t - tau) zeta~
+ *     (eq. (4.1)) and P = (t - tau)(x - Xi^{-1}) (eq. (3.9));
+ *   strategy 1 semi-Lagrangian (appendix B), after every step: departure point
+ *     Y = X - dt u(X, t_{n+1}) (eq. (B.2)), trapezoidal updates (B.4) of zeta~
+ *     and (B.5) of Xi^{-1}, written for eta = x - Xi^{-1}, with the gathers at Y
+ *     periodic bilinear or cubic (interp).
+ * float64 throughout.  Physical arrays N x N row-major as above.
+ * ------------------------------------------------------------------------- */
+typedef struct lm_e2d lm_e2d;
+typedef struct {
+  int32_t n;       /* 64, 128, 192, 256, 384, 512 or 1024 */
+  double dt;       /* time step, > 0 */
+  double U0, V0;   /* uniform flow added to u (0 for the paper's test) */
+  int32_t interp;  /* semi-Lagrangian gathers: LM_INTERP_BILINEAR or LM_INTERP_CUBIC */
+} lm_e2d_config;
+
+/* outputs of lm_e2d_end_interval, for lm_e2d_read */
+typedef enum {
+  LM_E2D_ZETA = 0,      /* vorticity at the end of the interval, zeta(x, tau + T)   */
+  LM_E2D_PS_MEAN = 1,   /* pseudospectral zeta~^L = g~ / T                           */
+  LM_E2D_PS_ETA_X = 2,  /* pseudospectral eta = x - Xi^{-1} = P / T (x component)    */
+  LM_E2D_PS_ETA_Y = 3,
+  LM_E2D_SL_MEAN = 4,   /* semi-Lagrangian zeta~^L                                   */
+  LM_E2D_SL_ETA_X = 5,  /* semi-Lagrangian eta                                       */
+  LM_E2D_SL_ETA_Y = 6
+} lm_e2d_kind;
+
+/* Allocate a flow (one device allocation).  LM_E_UNSUPPORTED for other n or
+   interp, LM_E_ARG for a non-positive or non-finite dt or non-finite U0, V0. */
+lm_status lm_e2d_create(const lm_e2d_config* cfg, void* hip_stream, lm_e2d** out);
+/* Set the vorticity (N x N float64; truncated to the mask).  Resets the step
+   counter; no interval is open.  Synchronous. */
+lm_status lm_e2d_set_vorticity(lm_e2d* e, const double* zeta, int on_device);
+/* Open an averaging interval at the current time (zeroes g~, P and the
+   semi-Lagrangian fields).  LM_E_STATE before lm_e2d_set_vorticity. */
+lm_status lm_e2d_begin_interval(lm_e2d* e);
+/* Advance nsteps >= 0 steps (dynamics, both strategy-1 forms).  Asynchronous. */
+lm_status lm_e2d_step(lm_e2d* e, int32_t nsteps);
+/* As lm_e2d_step with events: *ms_step = average step, *ms_sl = average
+   semi-Lagrangian kernel (milliseconds).  1 <= nsteps <= 4096.  Synchronous. */
+lm_status lm_e2d_step_profiled(lm_e2d* e, int32_t nsteps, double* ms_step, double* ms_sl);
+/* Close the interval (T = steps * dt) and compute the LM_E2D_* outputs.
+   LM_E_STATE without an open interval holding a step.  Synchronous. */
+lm_status lm_e2d_end_interval(lm_e2d* e, double* T_out);
+/* Copy one output (N x N float64).  LM_E_STATE before the first end. */
+lm_status lm_e2d_read(lm_e2d* e, int32_t kind, double* out, int on_device);
+/* Release (waits for the stream).  Null is a no-op. */
+lm_status lm_e2d_destroy(lm_e2d* e);
+
 const char* lm_status_str(lm_status s);
 /* Last error message of the calling thread ("" if none). */
 const char* lm_last_error(void);

@@ -4,8 +4,8 @@ advanced together in hand-written HIP kernels behind the C ABI of
 include/lagmean.h.  This package is the thin Python binding (``lagmean``), the
 build script (``build``) and the batch/serving drivers."""
 
-from .lagmean import (LagMeanError, Run, Batch, Config, make_config, footprint, load_library, OUTPUTS, REMAP_OUTPUTS, PEEK,
+from .lagmean import (LagMeanError, Run, Batch, Euler2D, Config, make_config, footprint, load_library, OUTPUTS, REMAP_OUTPUTS, PEEK,
                       LM_FIELD_H, LM_FIELD_ZETA)
 
-__all__ = ["LagMeanError", "Run", "Batch", "Config", "make_config", "footprint", "load_library", "OUTPUTS", "REMAP_OUTPUTS", "PEEK",
+__all__ = ["LagMeanError", "Run", "Batch", "Euler2D", "Config", "make_config", "footprint", "load_library", "OUTPUTS", "REMAP_OUTPUTS", "PEEK",
            "LM_FIELD_H", "LM_FIELD_ZETA"]

@@ -132,6 +132,11 @@ lm_status check_launch() {
 
 }  // namespace
 
+namespace lm {
+// the thread-local error of lm_last_error, for the other API source files
+__attribute__((visibility("hidden"))) lm_status api_fail(lm_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace lm
+
 extern "C" {
 
 const char* lm_status_str(lm_status s) {

@@ -18,6 +18,16 @@ template <int N> void launch_io_col_forward(RunView& r, const IoColFwd& J, int c
 template <int N> void launch_io_col_inverse(RunView& r, const IoColInv& J, int count);
 template <int N> void launch_io_row_inverse(RunView& r, const IoRowInv& J, int count);
 void launch_nonfinite(RunView& r, const double* a, size_t n, int* flag);
+// two-dimensional incompressible flow (float64): spectral multipliers, products,
+// Heun stages and the semi-Lagrangian update (euler2d_kernels.hip)
+void launch_e2d_spec(hipStream_t st, const Dims& d, const cplx<double>* Y, cplx<double>* S);
+void launch_e2d_products(hipStream_t st, int nn, const double* PH, double* NL, double s);
+void launch_e2d_stage(hipStream_t st, size_t sp, cplx<double>* Y, cplx<double>* Y1, cplx<double>* K1,
+                      const cplx<double>* R, double dt, int stage);
+void launch_e2d_sl(hipStream_t st, int N, const double* u, const double* v, const double* znext, const double* znow,
+                   const double* f_old, const double* ex_old, const double* ey_old, double* f_new, double* ex_new,
+                   double* ey_new, double* z_new, double dt, double m, bool cubic);
+
 // strategy-1 remap of the interval outputs (float64, N x N planes)
 void launch_remap_s1(RunView& r, const double* fh, const double* fz, const double* ex, const double* ey,
                      double* out, unsigned* best, int max_extent, unsigned long long* resid_bits);

@@ -55,6 +55,13 @@ class Config(ctypes.Structure):
                 ("interp", ctypes.c_int32), ("mode", ctypes.c_int32)]
 
 
+class E2DConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dt", ctypes.c_double), ("U0", ctypes.c_double), ("V0", ctypes.c_double),
+                ("interp", ctypes.c_int32)]
+
+
+E2D_OUTPUTS = {"zeta": 0, "PS_mean": 1, "PS_eta_x": 2, "PS_eta_y": 3, "SL_mean": 4, "SL_eta_x": 5, "SL_eta_y": 6}
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -87,6 +94,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_batch_step": [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
         "lm_batch_remaining": [P, P, ctypes.POINTER(ctypes.c_int32)],
         "lm_batch_destroy": [P],
+        "lm_e2d_create": [ctypes.POINTER(E2DConfig), P, ctypes.POINTER(P)],
+        "lm_e2d_set_vorticity": [P, P, ctypes.c_int],
+        "lm_e2d_begin_interval": [P],
+        "lm_e2d_step": [P, ctypes.c_int32],
+        "lm_e2d_step_profiled": [P, ctypes.c_int32, D, D],
+        "lm_e2d_end_interval": [P, D],
+        "lm_e2d_read": [P, ctypes.c_int32, P, ctypes.c_int],
+        "lm_e2d_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -280,3 +295,64 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Euler2D:
+    """Two-dimensional incompressible flow with strategy 1 pseudospectral and
+    semi-Lagrangian (wraps lm_e2d, float64)."""
+
+    def __init__(self, n: int, dt: float, *, U0: float = 0.0, V0: float = 0.0, interp: str = "bilinear",
+                 stream: int = 0):
+        self.lib = load_library()
+        self.N = n
+        self.h = ctypes.c_void_p(0)
+        cfg = E2DConfig(n=n, dt=dt, U0=U0, V0=V0, interp=LM_INTERP[interp])
+        _check(self.lib.lm_e2d_create(ctypes.byref(cfg), ctypes.c_void_p(stream), ctypes.byref(self.h)))
+
+    def close(self) -> None:
+        if self.h and self.h.value:
+            _check(self.lib.lm_e2d_destroy(self.h))
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_vorticity(self, zeta) -> None:
+        dev = _is_device(zeta)
+        a = zeta if dev else _host_in(zeta, self.N)
+        _check(self.lib.lm_e2d_set_vorticity(self.h, _ptr(a), 1 if dev else 0))
+
+    def begin_interval(self) -> None:
+        _check(self.lib.lm_e2d_begin_interval(self.h))
+
+    def step(self, nsteps: int = 1) -> None:
+        _check(self.lib.lm_e2d_step(self.h, int(nsteps)))
+
+    def step_profiled(self, nsteps: int):
+        """(average step, average semi-Lagrangian kernel) in milliseconds."""
+        a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(self.lib.lm_e2d_step_profiled(self.h, int(nsteps), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def end_interval(self) -> float:
+        T = ctypes.c_double(0.0)
+        _check(self.lib.lm_e2d_end_interval(self.h, ctypes.byref(T)))
+        return T.value
+
+    def read(self, kind: str, out=None):
+        if out is None:
+            out = np.empty((self.N, self.N))
+        _check(self.lib.lm_e2d_read(self.h, E2D_OUTPUTS[kind], _ptr(out), 1 if _is_device(out) else 0))
+        return out
+
+    def outputs(self) -> Dict[str, np.ndarray]:
+        return {k: self.read(k) for k in E2D_OUTPUTS}

@@ -8,7 +8,7 @@ full-grid L2 norm of each output (heights as h - H).
 
     python tests/golden/make_golden.py sw256_fp64 --stride 8
     python tests/golden/make_golden.py sw1024recipe_at256_fp32 --stride 8
-    python tests/golden/make_golden.py sw1024_fp32 --stride 16 --threads 6 --checkpoint /tmp/g1024.npz
+    python tests/golden/make_golden.py sw1024_fp32 --stride 16 --threads 6 --intervals 1 --checkpoint /tmp/g1024.npz
 
 The output is tests/golden/<workload>.npz.  With --checkpoint, the oracle's
 state is saved every --checkpoint-every steps and a rerun resumes from it.
@@ -63,19 +63,21 @@ def main(argv=None):
     ap.add_argument("--threads", type=int, default=8)
     ap.add_argument("--checkpoint", default=None)
     ap.add_argument("--checkpoint-every", type=int, default=250)
+    ap.add_argument("--intervals", type=int, default=0, help="store only the first K intervals (0 = all)")
     a = ap.parse_args(argv)
     olm.set_workers(a.threads)
     w = workload(a.workload)
     u, v, h = w.initial_state()
     r = olm.Run(olm.Params(N=w.N, dt=w.dt, f=w.f, g=w.g, H=w.H, nu8=w.nu8), u, v, h)
+    n_int = min(a.intervals, w.n_intervals) if a.intervals > 0 else w.n_intervals
     store = {"stride": a.stride, "offset": np.array(OFFSET), "N": w.N,
-             "steps_per_interval": w.steps_per_interval, "n_intervals": w.n_intervals}
+             "steps_per_interval": w.steps_per_interval, "n_intervals": n_int}
     i0 = k0 = 0
     if a.checkpoint and os.path.exists(a.checkpoint):
         i0, k0 = load_checkpoint(a.checkpoint, r, store)
         print(f"resumed at interval {i0} step {k0}", flush=True)
     t0 = time.time()
-    for i in range(i0, w.n_intervals):
+    for i in range(i0, n_int):
         if not (i == i0 and k0 > 0):
             r.begin_interval()
         for k in range(k0 if i == i0 else 0, w.steps_per_interval):
