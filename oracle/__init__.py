@@ -16,11 +16,14 @@ Contents
               form and eq. (3.9) for the inverse lift map (integrated as
               P = (t - tau)(x - Xi^{-1}), see ``lagmean``), and strategy 2,
               eqs. (4.5a,b) for the displacement xi and g-bar; plus the
-              Eulerian mean.
+              Eulerian mean; optionally (Params.momentum) the strategy-2 mean
+              of the momentum 1-form u . dx (appendix C, eq. (C.4)).
 ``tracker``   the definition oracle: brute-force particle tracking
               (eq. (2.1)) and time averaging along trajectories (eqs. (2.3),
-              (2.4), (3.1)), used only to check that ``lagmean`` converges to
-              the true means on small grids.
+              (2.4), (3.1)), and the pulled-back 1-form average of eq. (C.1)
+              with label derivatives from the variational equation, used only
+              to check that ``lagmean`` converges to the true means on small
+              grids.
 ``closed``    closed forms used as pins (exact kinematic plane-wave means,
               small-amplitude Stokes corrections, dispersion relation).
 ``euler2d``   two-dimensional incompressible inviscid flow (section 4.1) with

@@ -138,6 +138,7 @@ class Params:
     U0: float = 0.0                            # kinematic uniform flow
     V0: float = 0.0
     interp: str = "bilinear"                   # strategy-2 gathers: "bilinear" or "cubic"
+    momentum: bool = False                     # strategy-2 mean of the momentum 1-form (appendix C)
 
 
 class Grid:
@@ -252,6 +253,8 @@ class Run:
     # ------------------------------------------------------------------ state
     def _mean_keys(self):
         keys = ["xi_x", "xi_y", "P_x", "P_y"]
+        if self.p.momentum:
+            keys += ["gmom_x", "gmom_y"]
         for m in self.fields:
             keys += [f"gbar:{m}", f"gtil:{m}", f"E:{m}"]
         return keys
@@ -326,6 +329,25 @@ class Run:
             dg_dx = irfft2(G.ddx(Y[key]), N)
             dg_dy = irfft2(G.ddy(Y[key]), N)
             R[key] = D * rfft2(f_at - (wx * dg_dx + wy * dg_dy))
+        if p.momentum:
+            # appendix C, eq. (C.4) for the 1-form u . dx in the g-bar form of
+            # eq. (4.5b): with g = (t - tau) tau-bar and u-bar = w,
+            #   dg_i/dt + w_j d_j g_i + g_j d_i w_j = u_j(x + xi) (delta_ij + d_i xi_j)
+            # (the pull-back by Xi = x + xi on the right).  At t = tau, g = 0, so
+            # the d_i w_j term vanishes there and is only formed for s > 0.
+            dxi = {(c, d): irfft2((G.ddx if d == "x" else G.ddy)(Y[f"xi_{c}"]), N)
+                   for c in ("x", "y") for d in ("x", "y")}   # dxi[(j, i)] = d_i xi_j
+            gm = {c: irfft2(Y[f"gmom_{c}"], N) for c in ("x", "y")}
+            for i in ("x", "y"):
+                key = f"gmom_{i}"
+                src = u_at * ((1.0 if i == "x" else 0.0) + dxi[("x", i)]) \
+                    + v_at * ((1.0 if i == "y" else 0.0) + dxi[("y", i)])
+                dg_dx = irfft2(G.ddx(Y[key]), N)
+                dg_dy = irfft2(G.ddy(Y[key]), N)
+                rhs_i = src - (wx * dg_dx + wy * dg_dy)
+                if s > 0.0:
+                    rhs_i = rhs_i - (gm["x"] * dxi[("x", i)] + gm["y"] * dxi[("y", i)]) / s
+                R[key] = D * rfft2(rhs_i)
 
         # strategy 1: g-tilde, eq. (4.1), and P for the inverse lift map, eq. (3.9)
         for m in self.fields:
@@ -377,6 +399,9 @@ class Run:
             "S1_eta_x": irfft2(self.Y["P_x"], N) / T,
             "S1_eta_y": irfft2(self.Y["P_y"], N) / T,
         }
+        if self.p.momentum:
+            out["S2_mom_x"] = irfft2(self.Y["gmom_x"], N) / T
+            out["S2_mom_y"] = irfft2(self.Y["gmom_y"], N) / T
         for m in self.fields:
             c = field_offset(m, self.p)
             out[f"S2_mean:{m}"] = irfft2(self.Y[f"gbar:{m}"], N) / T + c
