@@ -61,9 +61,11 @@ typedef enum {
 
 typedef enum { LM_FP64 = 0, LM_FP32_MIXED = 1 } lm_precision;
 
-/* averaged fields (bit mask); the library averages h and zeta */
+/* averaged fields (bit mask); the library averages h and zeta, and on request
+   the momentum 1-form u . dx with strategy 2 (appendix C) */
 #define LM_F_H 1u
 #define LM_F_ZETA 2u
+#define LM_F_MOMENTUM 4u
 /* strategies (bit mask); the library always integrates all three */
 #define LM_S1 1u
 #define LM_S2 2u
@@ -85,7 +87,12 @@ typedef struct {
   double f, g, H;      /* Coriolis parameter, gravity, mean depth */
   double dt;           /* time step (shared by dynamics and mean PDEs) */
   double nu8;          /* eighth-order hyperviscosity on u, v, h (>= 0) */
-  uint32_t avg_fields; /* must be LM_F_H | LM_F_ZETA (or 0 for the default) */
+  uint32_t avg_fields; /* LM_F_H | LM_F_ZETA (or 0 for the default), optionally | LM_F_MOMENTUM:
+                          strategy 2 also integrates the mean of the momentum 1-form,
+                          eq. (C.4) in the g-bar form of eq. (4.5b):
+                          dg_i/dt + w_j d_j g_i + g_j d_i w_j = u_j(x + xi)(delta_ij + d_i xi_j)
+                          (two more prognostic fields, two more row tasks and
+                          column groups; a larger footprint) */
   uint32_t strategies; /* must be LM_S1 | LM_S2 | LM_EULER (or 0 for the default) */
   int32_t interp;      /* LM_INTERP_BILINEAR or LM_INTERP_CUBIC */
   int32_t mode;        /* LM_DYNAMIC */
@@ -148,7 +155,11 @@ typedef enum {
                              positions (field), after lm_remap_s1             */
   LM_K_S1_REMAP_XI_X = 8, /* strategy 1 remapped: Xi_x(y) - y, the end position
                              minus the mean position, as xi_x of strategy 2   */
-  LM_K_S1_REMAP_XI_Y = 9  /* strategy 1 remapped: Xi_y(y) - y                 */
+  LM_K_S1_REMAP_XI_Y = 9, /* strategy 1 remapped: Xi_y(y) - y                 */
+  LM_K_S2_MOM_X = 10,     /* strategy 2: the mean of the momentum 1-form at
+                             Lagrangian-mean positions, x component (runs
+                             created with LM_F_MOMENTUM; else LM_E_STATE)     */
+  LM_K_S2_MOM_Y = 11      /* same, y component                               */
 } lm_kind;
 typedef enum { LM_FIELD_H = 0, LM_FIELD_ZETA = 1 } lm_field;
 

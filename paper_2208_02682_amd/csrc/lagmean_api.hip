@@ -46,8 +46,9 @@ lm_status check_cfg(const lm_config* cfg) {
   if (!(cfg->nu8 >= 0.0) || !std::isfinite(cfg->nu8)) return fail(LM_E_ARG, "nu8 must be >= 0");
   if (!std::isfinite(cfg->f) || !std::isfinite(cfg->g) || !std::isfinite(cfg->H))
     return fail(LM_E_ARG, "f, g, H must be finite");
-  if (cfg->avg_fields != 0 && cfg->avg_fields != (LM_F_H | LM_F_ZETA))
-    return fail(LM_E_UNSUPPORTED, "averaged fields are h and zeta");
+  if (cfg->avg_fields != 0 && cfg->avg_fields != (LM_F_H | LM_F_ZETA) &&
+      cfg->avg_fields != (LM_F_H | LM_F_ZETA | LM_F_MOMENTUM))
+    return fail(LM_E_UNSUPPORTED, "averaged fields are h and zeta, optionally with the momentum 1-form");
   if (cfg->strategies != 0 && cfg->strategies != (LM_S1 | LM_S2 | LM_EULER))
     return fail(LM_E_UNSUPPORTED, "all of strategy 1, strategy 2 and the Eulerian mean are integrated");
   if (cfg->interp != LM_INTERP_BILINEAR && cfg->interp != LM_INTERP_CUBIC)
@@ -74,6 +75,7 @@ struct lm_batch {
     int N;
     bool fp32;
     bool cubic;
+    bool mom;
     void* d_desc = nullptr;  // device array of RunDesc<T>
     size_t cap = 0;          // bytes
     hipStream_t fork = nullptr;
@@ -119,7 +121,8 @@ lm_status copy_out(lm_run* r, double* dst, const double* src, int on_device) {
 lm_status zero_means(lm_run* r) {
   const size_t sp = r->d.spec_elems();
   const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
-  HIP_TRY(hipMemsetAsync(r->slab + r->L.Yr + lm::SF_GBH * sp * cT, 0, (lm::NSF_R - lm::SF_GBH) * sp * cT, r->stream));
+  const int nsf = r->mom ? lm::NSF_R : lm::SF_GMX;
+  HIP_TRY(hipMemsetAsync(r->slab + r->L.Yr + lm::SF_GBH * sp * cT, 0, (nsf - lm::SF_GBH) * sp * cT, r->stream));
   HIP_TRY(hipMemsetAsync(r->slab + r->L.Yd, 0, lm::NSF_D * sp * sizeof(cplx<double>), r->stream));
   return LM_OK;
 }
@@ -159,7 +162,8 @@ lm_status lm_query_footprint(const lm_config* cfg, size_t* bytes) {
   lm_status s = check_cfg(cfg);
   if (s != LM_OK) return s;
   if (!bytes) return fail(LM_E_ARG, "null bytes");
-  *bytes = lm::make_layout(lm::Dims::make(cfg->n), cfg->precision == LM_FP32_MIXED).total;
+  *bytes = lm::make_layout(lm::Dims::make(cfg->n), cfg->precision == LM_FP32_MIXED,
+                           (cfg->avg_fields & LM_F_MOMENTUM) != 0).total;
   return LM_OK;
 }
 
@@ -175,7 +179,8 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
   r->stream = (hipStream_t)hip_stream;
   r->fp32 = cfg->precision == LM_FP32_MIXED;
   r->cubic = cfg->interp == LM_INTERP_CUBIC;
-  r->L = lm::make_layout(r->d, r->fp32);
+  r->mom = (cfg->avg_fields & LM_F_MOMENTUM) != 0;
+  r->L = lm::make_layout(r->d, r->fp32, r->mom);
   r->n = r->n_tau = 0;
   r->has_state = r->in_interval = r->has_mean = r->has_remap = false;
   r->T = 0.0;
@@ -346,9 +351,29 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
     K.cb[p] = 0.0;
   }
   LM_DISPATCH_N(r->d.N, lm::launch_io_row_inverse, *r, K, 5);
+  if (r->mom) {
+    // the momentum 1-form mean g-bar_m / T (planes OUT_MOM, OUT_MOM + 1)
+    lm::IoColInv Jm{};
+    const size_t sp = r->d.spec_elems();
+    const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+    for (int q = 0; q < 2; ++q) {
+      Jm.src[q] = r->slab + r->L.Yr + (lm::SF_GMX + q) * sp * cT;
+      Jm.src_f32[q] = r->fp32 ? 1 : 0;
+      Jm.dst[q] = ioC + q * rf;
+    }
+    LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, Jm, 2);
+    lm::IoRowInv Km{};
+    Km.a[0] = ioC;
+    Km.b[0] = ioC + rf;
+    Km.oa[0] = out + lm::OUT_MOM * nn;
+    Km.ob[0] = out + (lm::OUT_MOM + 1) * nn;
+    Km.sa[0] = Km.sb[0] = 1.0 / T;
+    LM_DISPATCH_N(r->d.N, lm::launch_io_row_inverse, *r, Km, 1);
+  }
   int* flag = (int*)r->at(r->L.flag);
   HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), r->stream));
   lm::launch_nonfinite(*r, out, 10 * nn, flag);
+  if (r->mom) lm::launch_nonfinite(*r, out + lm::OUT_MOM * nn, 2 * nn, flag);
   lm_status s;
   if ((s = check_launch()) != LM_OK) return s;
   int hflag = 0;
@@ -404,9 +429,13 @@ lm_status lm_read_mean(lm_run* r, int32_t field, int32_t kind, double* out_, int
     case LM_K_S1_REMAP_MEAN: idx = lm::OUT_REMAP + field; break;
     case LM_K_S1_REMAP_XI_X: idx = lm::OUT_REMAP + 2; break;
     case LM_K_S1_REMAP_XI_Y: idx = lm::OUT_REMAP + 3; break;
+    case LM_K_S2_MOM_X: idx = lm::OUT_MOM; break;
+    case LM_K_S2_MOM_Y: idx = lm::OUT_MOM + 1; break;
     default: return fail(LM_E_ARG, "unknown kind");
   }
-  if (idx >= lm::OUT_REMAP && !r->has_remap) return fail(LM_E_STATE, "no strategy-1 remap of the last interval");
+  if (idx >= lm::OUT_MOM && !r->mom) return fail(LM_E_STATE, "the run does not average the momentum 1-form");
+  if (idx >= lm::OUT_REMAP && idx < lm::OUT_REMAP + 4 && !r->has_remap)
+    return fail(LM_E_STATE, "no strategy-1 remap of the last interval");
   const size_t nn = (size_t)r->d.N * r->d.N;
   lm_status s = copy_out(r, out_, (double*)r->at(r->L.out) + idx * nn, on_device);
   if (s != LM_OK) return s;
@@ -461,13 +490,14 @@ lm_status lm_destroy(lm_run* r) {
 // ---------------------------------------------------------------------------
 namespace {
 
-lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32, bool cubic) {
+lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32, bool cubic, bool mom) {
   for (auto& g : b->groups)
-    if (g.N == N && g.fp32 == fp32 && g.cubic == cubic) return &g;
+    if (g.N == N && g.fp32 == fp32 && g.cubic == cubic && g.mom == mom) return &g;
   lm_batch::Group g;
   g.N = N;
   g.fp32 = fp32;
   g.cubic = cubic;
+  g.mom = mom;
   if (hipStreamCreateWithFlags(&g.fork, hipStreamNonBlocking) != hipSuccess) return nullptr;
   if (hipEventCreateWithFlags(&g.join, hipEventDisableTiming) != hipSuccess) return nullptr;
   b->groups.push_back(g);
@@ -475,12 +505,13 @@ lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32, bool cubic) {
 }
 
 template <typename T>
-std::vector<char> group_descs(lm_batch* b, int N, bool fp32, bool cubic, const std::vector<int>& active,
+std::vector<char> group_descs(lm_batch* b, int N, bool fp32, bool cubic, bool mom, const std::vector<int>& active,
                               int* count) {
   std::vector<lm::RunDesc<T>> d;
   for (int i : active) {
     lm_run* r = b->members[i].run;
-    if (r->d.N == N && r->fp32 == fp32 && r->cubic == cubic) d.push_back(lm::run_desc<T>(*r, b->d_counters + i));
+    if (r->d.N == N && r->fp32 == fp32 && r->cubic == cubic && r->mom == mom)
+      d.push_back(lm::run_desc<T>(*r, b->d_counters + i));
   }
   *count = (int)d.size();
   std::vector<char> bytes(d.size() * sizeof(lm::RunDesc<T>));
@@ -509,13 +540,13 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
   std::vector<Launch> launches;
   for (int i : active) {
     lm_run* r = b->members[i].run;
-    lm_batch::Group* g = batch_group(b, r->d.N, r->fp32, r->cubic);
+    lm_batch::Group* g = batch_group(b, r->d.N, r->fp32, r->cubic, r->mom);
     if (!g) return fail(LM_E_HIP, "batch: stream or event creation failed");
   }
   for (auto& g : b->groups) {
     int count = 0;
-    std::vector<char> bytes = g.fp32 ? group_descs<float>(b, g.N, true, g.cubic, active, &count)
-                                     : group_descs<double>(b, g.N, false, g.cubic, active, &count);
+    std::vector<char> bytes = g.fp32 ? group_descs<float>(b, g.N, true, g.cubic, g.mom, active, &count)
+                                     : group_descs<double>(b, g.N, false, g.cubic, g.mom, active, &count);
     if (count == 0) continue;
     if (bytes.size() > g.cap) {
       if (g.d_desc) (void)hipFree(g.d_desc);
@@ -533,7 +564,7 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
   for (auto& l : launches) {
     if (e == hipSuccess) e = hipStreamWaitEvent(l.g->fork, b->fork_ev, 0);
     if (e == hipSuccess) {
-      LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32, l.g->cubic);
+      LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32, l.g->cubic, l.g->mom);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(l.g->join, l.g->fork);

@@ -34,17 +34,23 @@ void launch_columns_t(RunView& r, int stage) {
   cplx<T>* Ys[2] = {(cplx<T>*)r.at(r.L.Ys0), (cplx<T>*)r.at(r.L.Ys1)};
   const cplx<T>* Ys_in = Ys[r.ys_cur];
   cplx<T>* Ys_out = (stage < 0) ? Ys[r.ys_cur] : Ys[r.ys_cur ^ 1];
-  hipLaunchKernelGGL((k_columns<T, N>), col_grid<N>(r.d, NCG), col_block<N>(), 0, r.stream, P, r.d, r.ph, stage,
+  hipLaunchKernelGGL((k_columns<T, N>), col_grid<N>(r.d, r.mom ? NCG_MOM : NCG), col_block<N>(), 0, r.stream, P,
+                     r.d, r.ph, stage,
                      Ys_in, Ys_out);
   if (stage >= 0) r.ys_cur ^= 1;
 }
 
+// the rows pass of the mean right-hand sides, and the momentum rows when requested
 template <typename T, int N>
 void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
-  if (r.cubic)
-    hipLaunchKernelGGL((k_rows_rhs<T, N, true>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
-  else
-    hipLaunchKernelGGL((k_rows_rhs<T, N, false>), row_grid<N>(NRT), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d, sval);
+  const dim3 g = row_grid<N>(NRT), b(64 * ROW_WAVES);
+  if (r.cubic) hipLaunchKernelGGL((k_rows_rhs<T, N, true>), g, b, 0, r.stream, P, r.d, sval);
+  else hipLaunchKernelGGL((k_rows_rhs<T, N, false>), g, b, 0, r.stream, P, r.d, sval);
+  if (r.mom) {
+    const dim3 gm = row_grid<N>(2);
+    if (r.cubic) hipLaunchKernelGGL((k_rows_mom<T, N, true>), gm, b, 0, r.stream, P, r.d, sval);
+    else hipLaunchKernelGGL((k_rows_mom<T, N, false>), gm, b, 0, r.stream, P, r.d, sval);
+  }
 }
 
 template <typename T, int N>
@@ -122,7 +128,7 @@ hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms) {
 // one RK4 step of every run of one (N, precision) group: blockIdx.z selects
 // the run's descriptor
 template <typename T, int N>
-void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool cubic) {
+void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool cubic, bool mom) {
   const Dims d = Dims::make(N);
   for (int stage = 0; stage < 4; ++stage) {
     dim3 g1 = row_grid<N>(1);
@@ -130,18 +136,25 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool
     hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, dim3(64 * ROW_WAVES), 0, st, desc);
     dim3 g2 = row_grid<N>(NRT);
     g2.z = nruns;
-    if (cubic) hipLaunchKernelGGL((k_rows_rhs_b<T, N, true>), g2, dim3(64 * ROW_WAVES), 0, st, desc, stage);
-    else hipLaunchKernelGGL((k_rows_rhs_b<T, N, false>), g2, dim3(64 * ROW_WAVES), 0, st, desc, stage);
-    dim3 g3 = col_grid<N>(d, NCG);
+    const dim3 b2(64 * ROW_WAVES);
+    if (cubic) hipLaunchKernelGGL((k_rows_rhs_b<T, N, true>), g2, b2, 0, st, desc, stage);
+    else hipLaunchKernelGGL((k_rows_rhs_b<T, N, false>), g2, b2, 0, st, desc, stage);
+    if (mom) {
+      dim3 gm = row_grid<N>(2);
+      gm.z = nruns;
+      if (cubic) hipLaunchKernelGGL((k_rows_mom_b<T, N, true>), gm, b2, 0, st, desc, stage);
+      else hipLaunchKernelGGL((k_rows_mom_b<T, N, false>), gm, b2, 0, st, desc, stage);
+    }
+    dim3 g3 = col_grid<N>(d, mom ? NCG_MOM : NCG);
     g3.z = nruns;
     hipLaunchKernelGGL((k_columns_b<T, N>), g3, col_block<N>(), 0, st, desc, stage);
   }
 }
 
 template <int N>
-void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic) {
-  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns, cubic);
-  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns, cubic);
+void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic, bool mom) {
+  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns, cubic, mom);
+  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns, cubic, mom);
 }
 
 template <int N>
@@ -182,7 +195,7 @@ void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
 #define LM_INSTANTIATE(N)                                                                \
   namespace lm {                                                                         \
   template void launch_steps<N>(RunView&, int);                                          \
-  template void launch_batch_step<N>(hipStream_t, const void*, int, bool, bool);         \
+  template void launch_batch_step<N>(hipStream_t, const void*, int, bool, bool, bool);   \
   template hipError_t launch_steps_profiled<N>(RunView&, int, double*);                  \
   template void launch_prologue<N>(RunView&);                                            \
   template void launch_io_row_forward<N>(RunView&, const IoRowFwd&, int);                \

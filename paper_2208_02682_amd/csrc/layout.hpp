@@ -24,7 +24,8 @@ namespace lm {
 enum StateField : int {
   // working precision; the h accumulators (GBH, GTH, EH) integrate eta = h - H
   SF_U = 0, SF_V, SF_H, SF_GBH, SF_GBZ, SF_GTH, SF_GTZ, SF_EH, SF_EZ,
-  NSF_R = 9
+  SF_GMX, SF_GMY,  // strategy-2 g of the momentum 1-form (appendix C; used when requested)
+  NSF_R = 11
 };
 enum StateFieldD : int {
   SD_XIX = 0, SD_XIY, SD_PX, SD_PY,  // always float64 (displacement / position accumulators)
@@ -38,23 +39,28 @@ enum Inter : int {
   IC_GBH, IC_GBH_Y, IC_GBZ, IC_GBZ_Y,           // strategy-2 g
   IC_GTH, IC_GTH_Y, IC_GTZ, IC_GTZ_Y,           // strategy-1 g
   IC_PX, IC_PX_Y, IC_PY, IC_PY_Y,               // strategy-1 position accumulator P
-  NIC = 20
+  IC_GMX, IC_GMX_Y, IC_GMY, IC_GMY_Y,           // strategy-2 g of the momentum 1-form
+  NIC = 24
 };
 
 // row spectra: forward row transforms of the physical right-hand-side terms
 enum RowSpec : int {
   RS_ZV = 0, RS_ZU, RS_K, RS_HU, RS_HV,         // zeta v, zeta u, (u^2+v^2)/2, eta u, eta v
   RS_XIX, RS_XIY, RS_GBH, RS_GBZ, RS_GTH, RS_GTZ, RS_PX, RS_PY,
-  NRS = 13
+  RS_GMX, RS_GMY,
+  NRS = 15
 };
 
 // column-kernel work groups (one prognostic field each; E_h, E_zeta ride with h)
+// (the momentum groups come last and are launched only when requested)
 enum ColGroup : int {
   CG_U = 0, CG_V, CG_H, CG_XIX, CG_XIY, CG_GBH, CG_GBZ, CG_GTH, CG_GTZ, CG_PX, CG_PY,
-  NCG = 11
+  NCG = 11,
+  CG_GMX = 11, CG_GMY, NCG_MOM = 13
 };
 
-// row-kernel tasks of the right-hand-side pass
+// row-kernel tasks of the right-hand-side pass (the momentum rows, when
+// requested, are a kernel of their own with one task per component)
 enum RowTask : int { RT_XI = 0, RT_GB, RT_GT, RT_P, NRT = 4 };
 
 // 2/3-rule cutoff: modes |kx|, |ky| <= K are kept (a compile-time constant of N)

@@ -23,13 +23,16 @@ inline size_t slab_up(size_t x) { return (x + SLAB_ALIGN - 1) / SLAB_ALIGN * SLA
 // (mean h, zeta at mean positions, displacement x, y)
 constexpr int NOUT = 14;
 constexpr int OUT_REMAP = 10;
+constexpr int OUT_MOM = 14;  // momentum 1-form mean x, y (planes 14, 15), when requested
 
 // byte offsets of every buffer inside the slab
 struct Layout {
   size_t Yr, Yd, Ar, Ad, Ys0, Ys1, IC, RS, uvhz, tw64, twT, out, phys, ioC, flag, resid, total;
 };
 
-inline Layout make_layout(const Dims& d, bool fp32) {
+// mom: also room for the strategy-2 mean of the momentum 1-form (its state,
+// intermediates, row spectra and two output planes come last)
+inline Layout make_layout(const Dims& d, bool fp32, bool mom) {
   const size_t cT = fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
   const size_t cD = sizeof(cplx<double>);
   const size_t sp = d.spec_elems(), rf = d.rowfield_elems(), nn = (size_t)d.N * d.N;
@@ -40,18 +43,19 @@ inline Layout make_layout(const Dims& d, bool fp32) {
     o += slab_up(bytes);
     return at;
   };
-  L.Yr = take(NSF_R * sp * cT);
+  const int nsf = mom ? NSF_R : SF_GMX, nic = mom ? NIC : IC_GMX, nrs = mom ? NRS : RS_GMX;
+  L.Yr = take(nsf * sp * cT);
   L.Yd = take(NSF_D * sp * cD);
-  L.Ar = take(NSF_R * sp * cT);
+  L.Ar = take(nsf * sp * cT);
   L.Ad = take(NSF_D * sp * cD);
   L.Ys0 = take(3 * sp * cT);
   L.Ys1 = take(3 * sp * cT);
-  L.IC = take(NIC * rf * cT);
-  L.RS = take(NRS * rf * cT);
+  L.IC = take(nic * rf * cT);
+  L.RS = take(nrs * rf * cT);
   L.uvhz = take(nn * 4 * (fp32 ? sizeof(float) : sizeof(double)));
   L.tw64 = take((size_t)d.N * cD);
   L.twT = take((size_t)d.N * cT);
-  L.out = take(NOUT * nn * sizeof(double));
+  L.out = take((mom ? NOUT + 2 : NOUT) * nn * sizeof(double));
   L.phys = take(3 * nn * sizeof(double));
   L.ioC = take(10 * rf * cD);
   L.flag = take(sizeof(int));
@@ -66,6 +70,7 @@ struct RunView {
   hipStream_t stream;
   bool fp32;
   bool cubic;        // cubic strategy-2 gathers (else bilinear)
+  bool mom;          // strategy-2 mean of the momentum 1-form as well
   Layout L;
   char* slab;
   int64_t n, n_tau;  // steps since set_state; step index at the interval start

@@ -334,6 +334,28 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims
 //   RT_GT  strategy 1, g-tilde of eta and zeta (eq. (4.1))
 //   RT_P   strategy 1, both P components (eq. (3.9) in P form)
 // The two strategy-2 tasks each transform xi and gather at x + xi.
+// gathers of (u, v) (PAIR 0) or (eta, zeta) (PAIR 1) at x + xi for the E points
+// of a lane, in place of the displacements held in a
+template <typename T, int N, bool CUB, int PAIR>
+__device__ __forceinline__ void gather_row(cplx<T> (&a)[fft_E<N>()], const P4<T>* __restrict__ F, int t, int y) {
+  constexpr int E = fft_E<N>(), NT = N / E;
+  if constexpr (CUB) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      a[e] = gather2_cubic<T, N, PAIR>(F, t + NT * e, y, a[e].x, a[e].y);
+      sched_fence();
+    }
+  } else {
+    constexpr int GG = 4;
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += GG) {
+#pragma unroll
+      for (int e = e0; e < e0 + GG; ++e) a[e] = gather2<T, N, PAIR>(F, t + NT * e, y, a[e].x, a[e].y);
+      sched_fence();
+    }
+  }
+}
+
 template <typename T, int N, bool CUB>
 __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
                                               int task, cplx<T>* lds) {
@@ -450,6 +472,97 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims
   int rowblock, task, z;
   xcd_split(gridDim.x, gridDim.y, rowblock, task, z);  // grid = (row blocks, tasks)
   rows_rhs_body<T, N, CUB>(P, d, s, rowblock, task, lds);
+}
+
+// --------------------------------------------------------------------------
+// rows_mom: the strategy-2 mean of the momentum 1-form (appendix C, eq. (C.4)
+// in the g-bar form of eq. (4.5b)), launched after rows_rhs when requested.
+// Component i = x (task 0) or y (task 1):
+//   R_i = u_j(x + xi)(delta_ij + d_i xi_j) - w_j d_j g_i - g_j d_i xi_j / s
+// (w = xi / s, or u / 2 at s = 0, where g = 0 and the last term is not formed).
+// Order of work keeps at most three lane arrays live beside a transform.
+// --------------------------------------------------------------------------
+template <typename T, int N, bool CUB>
+__device__ __forceinline__ void rows_mom_body(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
+                                              int task, cplx<T>* lds) {
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT;
+  const int grp = row_group<NT>(), t = threadIdx.x % NT;
+  const int y = rowblock * G::RPB + grp;
+  cplx<T>* buf = lds + grp * G::L;
+  const size_t rf = d.rowfield_elems();
+  const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
+  cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
+  const P4<T>* F = P.uvhz;
+  const P4<T>* Fr = P.uvhz + (size_t)y * N;
+  const bool ix = (task == 0);
+  cplx<T> a[E], b[E], c[E];
+  // d_i xi_x, d_i xi_y: i kx in the row pass for i = x, the column pass's i ky versions for i = y
+  if (ix) load_pair<T, N, true, true>(b, ICr + IC_XIX * rf, ICr + IC_XIY * rf, t);
+  else load_pair<T, N, false, false>(b, ICr + IC_XIX_Y * rf, ICr + IC_XIY_Y * rf, t);
+  inverse_row<T, N>(b, buf, t, P.tw);
+  // stretching: a.x = -(g_x d_i xi_x + g_y d_i xi_y) / s
+  if (s > 0.0) {
+    load_pair<T, N, false, false>(c, ICr + IC_GMX * rf, ICr + IC_GMY * rf, t);
+    inverse_row<T, N>(c, buf, t, P.tw);
+    const T inv_s = T(1.0 / s);
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = {-(c[e].x * b[e].x + c[e].y * b[e].y) * inv_s, T(0)};
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = {T(0), T(0)};
+  }
+  // xi (kept until the gathers consume it)
+  load_pair<T, N, false, false>(c, ICr + IC_XIX * rf, ICr + IC_XIY * rf, t);
+  inverse_row<T, N>(c, buf, t, P.tw);
+  // advection: a.x -= w . grad g_i with w = xi / s (u / 2 at s = 0), formed on the fly
+  {
+    cplx<T> dg[E];
+    const int gi = ix ? IC_GMX : IC_GMY;
+    load_pair<T, N, true, false>(dg, ICr + gi * rf, ICr + (gi + 1) * rf, t);
+    inverse_row<T, N>(dg, buf, t, P.tw);
+    if (s > 0.0) {
+      const T inv_s = T(1.0 / s);
+#pragma unroll
+      for (int e = 0; e < E; ++e) a[e].x = a[e].x - (c[e].x * inv_s * dg[e].x + c[e].y * inv_s * dg[e].y);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const P4<T> q = Fr[t + NT * e];
+        a[e].x = a[e].x - (T(0.5) * q.u * dg[e].x + T(0.5) * q.v * dg[e].y);
+      }
+    }
+  }
+  // the gathered (u, v) at x + xi and the pulled-back source (consumes xi)
+  const T dxi = ix ? T(1) : T(0), dyi = ix ? T(0) : T(1);
+  if constexpr (CUB) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cplx<T> g = gather2_cubic<T, N, 0>(F, t + NT * e, y, c[e].x, c[e].y);
+      a[e].x = a[e].x + (g.x * (dxi + b[e].x) + g.y * (dyi + b[e].y));
+      sched_fence();
+    }
+  } else {
+    constexpr int GG = 4;
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += GG) {
+#pragma unroll
+      for (int e = e0; e < e0 + GG; ++e) {
+        const cplx<T> g = gather2<T, N, 0>(F, t + NT * e, y, c[e].x, c[e].y);
+        a[e].x = a[e].x + (g.x * (dxi + b[e].x) + g.y * (dyi + b[e].y));
+      }
+      sched_fence();
+    }
+  }
+  forward_row<T, N, false>(a, buf, t, P.tw, RSr + (ix ? RS_GMX : RS_GMY) * rf, nullptr);
+}
+
+template <typename T, int N, bool CUB>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom(StepPtrs<T> P, Dims d, double s) {
+  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+  int rowblock, task, z;
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);  // grid = (row blocks, 2 components)
+  rows_mom_body<T, N, CUB>(P, d, s, rowblock, task, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -577,7 +690,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
   constexpr int F0 = (G == CG_U) ? RS_ZV : (G == CG_V) ? RS_ZU : (G == CG_H) ? RS_HU
                    : (G == CG_XIX) ? RS_XIX : (G == CG_XIY) ? RS_XIY : (G == CG_GBH) ? RS_GBH
                    : (G == CG_GBZ) ? RS_GBZ : (G == CG_GTH) ? RS_GTH : (G == CG_GTZ) ? RS_GTZ
-                   : (G == CG_PX) ? RS_PX : RS_PY;
+                   : (G == CG_PX) ? RS_PX : (G == CG_PY) ? RS_PY : (G == CG_GMX) ? RS_GMX : RS_GMY;
   constexpr int F1 = (G == CG_U || G == CG_V) ? RS_K : RS_HV;
   cplx<T> r0[E], r1[E];
   if (stage >= 0) {
@@ -594,7 +707,8 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     A = P.Ad + sd * sp;
   } else {
     constexpr int sr = (G == CG_U) ? SF_U : (G == CG_V) ? SF_V : (G == CG_H) ? SF_H : (G == CG_GBH) ? SF_GBH
-                     : (G == CG_GBZ) ? SF_GBZ : (G == CG_GTH) ? SF_GTH : SF_GTZ;
+                     : (G == CG_GBZ) ? SF_GBZ : (G == CG_GTH) ? SF_GTH : (G == CG_GTZ) ? SF_GTZ
+                     : (G == CG_GMX) ? SF_GMX : SF_GMY;
     Y = reinterpret_cast<cplx<TS>*>(P.Yr) + sr * sp;
     A = reinterpret_cast<cplx<TS>*>(P.Ar) + sr * sp;
   }
@@ -668,7 +782,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
   } else {
     constexpr int o = (G == CG_XIX) ? IC_XIX : (G == CG_XIY) ? IC_XIY : (G == CG_GBH) ? IC_GBH
                     : (G == CG_GBZ) ? IC_GBZ : (G == CG_GTH) ? IC_GTH : (G == CG_GTZ) ? IC_GTZ
-                    : (G == CG_PX) ? IC_PX : IC_PY;
+                    : (G == CG_PX) ? IC_PX : (G == CG_PY) ? IC_PY : (G == CG_GMX) ? IC_GMX : IC_GMY;
     column_inverse<T, N, C, TS, false>(cx, S, P.IC + o * rf, d, P.tw);
     column_inverse<T, N, C, TS, true>(cx, S, P.IC + (o + 1) * rf, d, P.tw);
   }
@@ -701,6 +815,8 @@ __device__ __forceinline__ void columns_body(const StepPtrs<T>& P, const Dims& d
     case CG_GTZ: column_group<T, N, C, CG_GTZ>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
     case CG_PX: column_group<T, N, C, CG_PX>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
     case CG_PY: column_group<T, N, C, CG_PY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_GMX: column_group<T, N, C, CG_GMX>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+    case CG_GMY: column_group<T, N, C, CG_GMY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
     default: break;
   }
 }
@@ -736,6 +852,17 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>*
   const double c = (stage == 0) ? 0.0 : ((stage == 3) ? 1.0 : 0.5);
   const double s = (double(*R.counter) + c) * R.ph.dt;
   rows_rhs_body<T, N, CUB>(R.P, Dims::make(N), s, rowblock, task, lds);
+}
+
+template <typename T, int N, bool CUB>
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom_b(const RunDesc<T>* __restrict__ runs, int stage) {
+  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+  int rowblock, task, z;
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);
+  const RunDesc<T>& R = runs[z];
+  const double c = (stage == 0) ? 0.0 : ((stage == 3) ? 1.0 : 0.5);
+  const double s = (double(*R.counter) + c) * R.ph.dt;
+  rows_mom_body<T, N, CUB>(R.P, Dims::make(N), s, rowblock, task, lds);
 }
 
 // stage parity selects the stage-value buffers: between steps the current

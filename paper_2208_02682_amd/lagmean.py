@@ -22,7 +22,8 @@ STATUS = {0: "LM_OK", -1: "LM_E_ARG", -2: "LM_E_STATE", -3: "LM_E_OOM", -4: "LM_
           -5: "LM_E_NONFINITE", -6: "LM_E_UNSUPPORTED", -7: "LM_E_BUDGET"}
 LM_FP64, LM_FP32_MIXED = 0, 1
 (LM_K_S2_MEAN, LM_K_S2_XI_X, LM_K_S2_XI_Y, LM_K_S1_MEAN, LM_K_S1_ETA_X, LM_K_S1_ETA_Y, LM_K_EULER_MEAN,
- LM_K_S1_REMAP_MEAN, LM_K_S1_REMAP_XI_X, LM_K_S1_REMAP_XI_Y) = range(10)
+ LM_K_S1_REMAP_MEAN, LM_K_S1_REMAP_XI_X, LM_K_S1_REMAP_XI_Y, LM_K_S2_MOM_X, LM_K_S2_MOM_Y) = range(12)
+LM_F_H, LM_F_ZETA, LM_F_MOMENTUM = 1, 2, 4
 LM_FIELD_H, LM_FIELD_ZETA = 0, 1
 PEEK = {"u": 0, "v": 1, "h": 2, "gbar:h": 3, "gbar:zeta": 4, "gtil:h": 5, "gtil:zeta": 6,
         "E:h": 7, "E:zeta": 8, "xi_x": 9, "xi_y": 10, "P_x": 11, "P_y": 12}
@@ -34,6 +35,8 @@ OUTPUTS = {
     "S1_eta_x": (0, LM_K_S1_ETA_X), "S1_eta_y": (0, LM_K_S1_ETA_Y),
     "E_mean:h": (LM_FIELD_H, LM_K_EULER_MEAN), "E_mean:zeta": (LM_FIELD_ZETA, LM_K_EULER_MEAN),
 }
+# strategy-2 mean of the momentum 1-form (runs made with momentum=True)
+MOMENTUM_OUTPUTS = {"S2_mom_x": (0, LM_K_S2_MOM_X), "S2_mom_y": (0, LM_K_S2_MOM_Y)}
 # outputs of lm_remap_s1 (strategy 1 at Lagrangian-mean positions)
 REMAP_OUTPUTS = {
     "S1R_mean:h": (LM_FIELD_H, LM_K_S1_REMAP_MEAN), "S1R_mean:zeta": (LM_FIELD_ZETA, LM_K_S1_REMAP_MEAN),
@@ -125,9 +128,10 @@ LM_INTERP = {"bilinear": 0, "cubic": 1}
 
 
 def make_config(n: int, *, precision: str = "fp64", f: float = 1.0, g: float = 1.0, H: float = 1.0,
-                dt: float, nu8: float = 0.0, interp: str = "bilinear") -> Config:
+                dt: float, nu8: float = 0.0, interp: str = "bilinear", momentum: bool = False) -> Config:
     prec = {"fp64": LM_FP64, "fp32": LM_FP32_MIXED}[precision]
-    return Config(n=n, precision=prec, f=f, g=g, H=H, dt=dt, nu8=nu8, avg_fields=0, strategies=0,
+    fields = (LM_F_H | LM_F_ZETA | LM_F_MOMENTUM) if momentum else 0
+    return Config(n=n, precision=prec, f=f, g=g, H=H, dt=dt, nu8=nu8, avg_fields=fields, strategies=0,
                   interp=LM_INTERP[interp], mode=0)
 
 
@@ -231,6 +235,9 @@ class Run:
         res = ctypes.c_double(0.0)
         _check(self.lib.lm_remap_s1(self.h, int(max_extent), ctypes.byref(res)))
         return res.value
+
+    def momentum_outputs(self) -> Dict[str, np.ndarray]:
+        return {name: self.read_mean(fk[0], fk[1]) for name, fk in MOMENTUM_OUTPUTS.items()}
 
     def remap_outputs(self) -> Dict[str, np.ndarray]:
         return {name: self.read_mean(fk[0], fk[1]) for name, fk in REMAP_OUTPUTS.items()}
