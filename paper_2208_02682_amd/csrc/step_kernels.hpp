@@ -604,18 +604,31 @@ struct ColCtx {
   bool valid;       // kx <= K
 };
 
-// block-wide: rows of a [N][NKXP] field (columns kx0..kx0+C-1) into the C buffers
+// block-wide: rows of a [N][NKXP] field (columns kx0..kx0+C-1) into the C buffers.
+// A thread keeps one column c and visits rows y = threadIdx.x / C + NT k; four
+// loads are in flight before their values go to LDS (all E at once would push
+// the column kernel past 128 VGPRs, the limit for 4 waves per SIMD).
 template <typename T, int N, int C>
 __device__ __forceinline__ void tile_load(const ColCtx<T, N, C>& cx, const cplx<T>* __restrict__ src,
                                           const Dims& d) {
-  constexpr int LC = ColCtx<T, N, C>::LC;
+  constexpr int LC = ColCtx<T, N, C>::LC, E = fft_E<N>(), NT = N / E, U = 4;
+  const int c = threadIdx.x % C, y0 = threadIdx.x / C;
+  const bool in = cx.kx0 + c <= kcut<N>();
+  const unsigned o0 = (unsigned)y0 * (unsigned)d.NKXP + (unsigned)(cx.kx0 + c);
+  const unsigned dy = (unsigned)NT * (unsigned)d.NKXP;
+  cplx<T>* dstl = cx.lds + c * LC;
   __syncthreads();
-  for (int i = threadIdx.x; i < N * C; i += blockDim.x) {
-    const int c = i % C, y = i / C;
-    const int kx = cx.kx0 + c;
-    cplx<T> val = {T(0), T(0)};
-    if (kx <= kcut<N>()) val = src[(size_t)y * d.NKXP + kx];
-    cx.lds[c * LC + pidx(y)] = val;
+#pragma unroll
+  for (int k0 = 0; k0 < E; k0 += U) {
+    cplx<T> val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      val[u] = {T(0), T(0)};
+      if (k0 + u < E && in) val[u] = src[o0 + (unsigned)(k0 + u) * dy];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < E) dstl[pidx(y0 + NT * (k0 + u))] = val[u];
   }
   __syncthreads();
 }
@@ -821,8 +834,16 @@ __device__ __forceinline__ void columns_body(const StepPtrs<T>& P, const Dims& d
   }
 }
 
+// float32: ask for 4 resident waves per SIMD (at most 128 VGPRs) where the kernel
+// reaches that without spilling; at 512, and in the batched kernel at 1024, the
+// same request spills, and float64 is out of its reach
+template <typename T, int N, bool BATCHED>
+__host__ __device__ constexpr int col_waves() {
+  return (sizeof(T) == 4 && N != 512 && !(BATCHED && N == 1024)) ? 4 : 1;
+}
+
 template <typename T, int N>
-__global__ void __launch_bounds__(col_threads<N>())
+__global__ void __launch_bounds__(col_threads<N>(), (col_waves<T, N, false>()))
     k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out) {
   __shared__ cplx<T> lds[col_tile<N>() * col_buf(N)];
   int tile, group, z;
@@ -868,7 +889,7 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom_b(const RunDesc<T>*
 // stage parity selects the stage-value buffers: between steps the current
 // stage input is always Ys0 (four swaps per step)
 template <typename T, int N>
-__global__ void __launch_bounds__(col_threads<N>()) k_columns_b(const RunDesc<T>* __restrict__ runs, int stage) {
+__global__ void __launch_bounds__(col_threads<N>(), (col_waves<T, N, true>())) k_columns_b(const RunDesc<T>* __restrict__ runs, int stage) {
   __shared__ cplx<T> lds[col_tile<N>() * col_buf(N)];
   int tile, group, z;
   xcd_split(gridDim.x, gridDim.y, tile, group, z);
