@@ -25,7 +25,11 @@ Three more modes print one JSON line each:
                  and at a sustainable rate (offered load 0.7 of the measured capacity);
   --mode euler : the two-dimensional incompressible test (two vortices, 128^2,
                  T = 25) with strategy 1 pseudospectral and semi-Lagrangian, and
-                 the semi-Lagrangian kernel at 1024^2 against HBM.
+                 the semi-Lagrangian kernel at 1024^2 against HBM;
+  --mode tune  : the autotuner over every grid size and precision, written to the
+                 schedule cache (paper_2208_02682_amd/schedules_<arch>.json).
+Every mode applies the shipped schedule cache first (--no-schedule-cache: the
+default schedules); --autotune measures the mode's own sizes first.
 """
 
 from __future__ import annotations
@@ -42,7 +46,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sw1024_fp32_hbm_traffic.md")
-KERNEL_SOURCES = ["fft_core.hpp", "layout.hpp", "step_kernels.hpp"]
+KERNEL_SOURCES = ["fft_core.hpp", "col_tile.hpp", "layout.hpp", "step_kernels.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -54,9 +58,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, schedule=None):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, or
-    None when it was taken for other kernel sources or another workload."""
+    None when it was taken for other kernel sources, another workload or another
+    launch schedule."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -67,6 +72,8 @@ def measured_traffic(kernel: str, workload: str):
         if len(parts) >= 2 and parts[0].endswith(":"):
             fields[parts[0][:-1]] = parts[1]
     if fields.get("source_sha256") != kernel_source_hash() or fields.get("workload") != workload:
+        return None
+    if schedule is not None and fields.get("schedule") != f"{schedule[0]},{schedule[1]}":
         return None
     v = fields.get(f"traffic_bytes_{kernel}")
     return float(v) if v is not None else None
@@ -134,6 +141,48 @@ def _cfg(w, precision=None):
     return make_config(w.N, precision=precision or w.precision, f=w.f, g=w.g, H=w.H, dt=w.dt, nu8=w.nu8)
 
 
+def apply_schedules(a, specs, config_for, state_for) -> str:
+    """Launch schedules for this run: the shipped cache of the device's
+    architecture (unless --no-schedule-cache), then, with --autotune, fresh
+    measurements of specs ((N, precision) pairs), saved to --schedules-out if
+    given.  Returns where the schedules came from."""
+    from paper_2208_02682_amd import autotune as at
+    arch = at.device_arch()
+    source = "default"
+    if not a.no_schedule_cache and at.load_default(arch):
+        source = "cache"
+    if a.autotune:
+        tuned = at.tune(specs, config_for, state_for)
+        source = "autotune"
+        for t in tuned:
+            print(f"autotune: N={t['n']} {t['precision']}: best {t['best']} "
+                  + ", ".join(f"{k}: {v:.4f} ms" for k, v in t["ms"].items()), file=sys.stderr, flush=True)
+        if a.schedules_out:
+            at.merge_save(a.schedules_out, arch, tuned)
+    return source
+
+
+def bench_tune(a) -> dict:
+    """The autotuner over every grid size and precision; writes the cache."""
+    import torch
+    from paper_2208_02682_amd import autotune as at
+    from synth.workloads import scaled_run
+    torch.cuda.set_device(0)
+    sizes = (64, 128, 192, 256, 384, 512, 1024)
+    ws = {N: scaled_run(N, Ro=0.1, ratio=1.0, periods=1.0, seeds=(5, 6)) for N in sizes}
+    states = dict(zip(sizes, generate_states([ws[N] for N in sizes])))
+    specs = [(N, p) for N in sizes for p in ("fp32", "fp64")]
+    a.autotune, a.no_schedule_cache = True, True
+    if not a.schedules_out:
+        a.schedules_out = at.cache_path(at.device_arch())
+    t0 = time.perf_counter()
+    apply_schedules(a, specs, lambda N, p: _cfg(ws[N], p), lambda N: states[N])
+    from paper_2208_02682_amd import get_schedule
+    return {"mode": "tune", "arch": at.device_arch(), "seconds": time.perf_counter() - t0,
+            "cache": os.path.relpath(a.schedules_out, ROOT),
+            "schedules": {f"{N}:{p}": list(get_schedule(N, p)) for N, p in specs}}
+
+
 def bench_batch(a) -> dict:
     """Config of 64 uneven runs: batched against alone, and against float64 alone."""
     import numpy as np
@@ -145,6 +194,13 @@ def bench_batch(a) -> dict:
     states = generate_states(ws)
     torch.cuda.set_device(0)
     pts = sum(w.N * w.N * w.steps_per_interval for w in ws)
+    first = {}
+    for w, st in zip(ws, states):
+        first.setdefault(w.N, (w, st))
+    sizes = sorted(first)
+    source = apply_schedules(a, [(N, p) for N in sizes for p in ("fp32", "fp64")],
+                             lambda N, p: _cfg(first[N][0], p), lambda N: first[N][1])
+    from paper_2208_02682_amd import get_schedule
 
     def start(run, st):
         run.set_state(*st)
@@ -204,7 +260,6 @@ def bench_batch(a) -> dict:
     print(f"batch: the same runs alone in {t_alone:.2f} s", file=sys.stderr, flush=True)
     t_fp64, _ = sequential("fp64", False)
     print(f"batch: float64 runs alone in {t_fp64:.2f} s", file=sys.stderr, flush=True)
-    sizes = sorted({w.N for w in ws})
     return {
         "metric": f"aggregate grid-pt RK4 steps/s, {len(ws)} uneven runs batched", "value": pts / t_batch,
         "unit": "grid-pt RK4 steps/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32+f64",
@@ -213,7 +268,9 @@ def bench_batch(a) -> dict:
                                f"xi and P, Ro ~ U[0.02, 0.2], wave/vortex energy ratio log-U[0.25, 4], "
                                f"T ~ U[1, 8] wave periods, dt = 0.64/N",
                    "runs": len(ws), "total_steps": sum(w.steps_per_interval for w in ws),
-                   "grid_point_steps": pts, "tick_steps": a.tick_steps},
+                   "grid_point_steps": pts, "tick_steps": a.tick_steps,
+                   "schedules": {f"{N}:{p}": list(get_schedule(N, p)) for N in sizes for p in ("fp32", "fp64")},
+                   "schedule_source": source},
         "seconds": {"batched": t_batch, "alone_sequential": t_alone, "fp64_alone_sequential": t_fp64},
         "alone_sequential_value": pts / t_alone, "fp64_alone_sequential_value": pts / t_fp64,
         "speedup_vs_alone": t_alone / t_batch, "speedup_vs_fp64_alone": t_fp64 / t_batch,
@@ -298,6 +355,11 @@ def bench_serve(a) -> dict:
     states = generate_states([r.run for r in reqs])
     print(f"serve: {len(reqs)} request states generated", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
+    first = {}
+    for r, st in zip(reqs, states):
+        first.setdefault(r.run.N, (r.run, st))
+    source = apply_schedules(a, [(N, "fp32") for N in sizes], lambda N, p: _cfg(first[N][0], p),
+                             lambda N: first[N][1])
     mean_work = float(np.mean([r.run.N * r.run.N * r.run.steps_per_interval for r in reqs]))
     main = _serve_once(reqs, states, a.rate, a.window, a, a.window + a.drain_limit)
     rec = {"metric": "p50/p99 solve latency (arrival to means on the host), Poisson arrivals",
@@ -307,7 +369,8 @@ def bench_serve(a) -> dict:
                                   f"64^2 recipe scaled to N, float32 transforms with float64 xi and P, "
                                   f"T ~ U[1, 8] wave periods, dt = 0.64/N, arrival seed 7",
                       "mean_grid_point_steps_per_request": mean_work, "hbm_budget_gib": a.hbm_budget_gib,
-                      "max_resident_points": a.max_resident_points, "tick_steps": a.tick_steps},
+                      "max_resident_points": a.max_resident_points, "tick_steps": a.tick_steps,
+                      "schedule_source": source},
            "offered": main}
     if a.sustainable_window > 0 and np.isfinite(main["capacity_pt_steps_per_s"]):
         rate = 0.7 * main["capacity_pt_steps_per_s"] / mean_work
@@ -383,7 +446,13 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed replay (roofline fields become null)")
-    ap.add_argument("--mode", choices=("step", "batch", "serve", "euler"), default="step")
+    ap.add_argument("--mode", choices=("step", "batch", "serve", "euler", "tune"), default="step")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure the launch schedules of the mode's grid sizes first (lm_autotune)")
+    ap.add_argument("--no-schedule-cache", action="store_true",
+                    help="do not apply the shipped schedule cache (default schedules unless --autotune)")
+    ap.add_argument("--schedules-out", default=None, metavar="PATH",
+                    help="with --autotune (or --mode tune): write the choices to this JSON cache")
     ap.add_argument("--batch-runs", type=int, default=64)
     ap.add_argument("--tick-steps", type=int, default=32, help="batch/serve: steps per lm_batch_step call")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
@@ -403,8 +472,8 @@ def main(argv=None) -> int:
               f"--gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
 
-    if a.mode in ("batch", "serve", "euler"):
-        rec = {"batch": bench_batch, "serve": bench_serve, "euler": bench_euler}[a.mode](a)
+    if a.mode in ("batch", "serve", "euler", "tune"):
+        rec = {"batch": bench_batch, "serve": bench_serve, "euler": bench_euler, "tune": bench_tune}[a.mode](a)
         print(json.dumps(rec), flush=True)
         return 0
     import numpy as np
@@ -427,6 +496,9 @@ def main(argv=None) -> int:
     stream = torch.cuda.current_stream()
     u, v, h = w.initial_state()
     fields = [torch.from_numpy(x).cuda() for x in (u, v, h)]
+    source = apply_schedules(a, [(w.N, w.precision)], lambda N, p: _cfg(w, p), lambda N: (u, v, h))
+    from paper_2208_02682_amd import get_schedule
+    sched = get_schedule(w.N, w.precision)
     run = Run(make_config(w.N, precision=w.precision, f=w.f, g=w.g, H=w.H, dt=w.dt, nu8=w.nu8),
               stream=stream.cuda_stream)
 
@@ -493,10 +565,11 @@ def main(argv=None) -> int:
                                f"and Eulerian means of h and zeta in the same RK4 stages",
                    "N": w.N, "precision": "float32 transforms/products/gathers, float64 xi and P state"
                    if fp32 else "float64", "dt": w.dt, "nu8": w.nu8, "steps_per_interval": w.steps_per_interval,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "schedule": {"col_tile": sched[0], "xcd_order": sched[1], "source": source}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic(dom, w.name),
+                     "traffic": measured_traffic(dom, w.name, sched),
                      "alg_bytes_per_launch": kernels[dom]["alg_bytes"], "avg_launch_ms": kernels[dom]["avg_ms"]},
         "kernels": kernels,
         "step_alg_bytes_per_point": step_bytes / pts,

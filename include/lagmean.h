@@ -245,7 +245,51 @@ lm_status lm_batch_remaining(lm_batch* b, const lm_run* run, int32_t* remaining)
 /* Release the batch (members are removed, not destroyed).  Null is a no-op. */
 lm_status lm_batch_destroy(lm_batch* b);
 
-/* Text of a status code (static storage). */
+/* ---------------------------------------------------------------------------
+ * Launch schedules and the autotuner.  The time-stepping kernels of one
+ * (n, precision) can be launched in several ways that compute the same numbers
+ * in the same order (results are bit-identical across schedules):
+ *   col_tile   width of the column tiles of the column pass (columns per
+ *              block): -1 half, 0 the default (8 columns when a transform
+ *              spans at least 8 lanes), +1 twice; a width is usable when its
+ *              block is whole wavefronts of at most 1024 threads and its LDS
+ *              tile fits in a CU's 160 KiB;
+ *   xcd_order  1: blocks renumbered so that each of the 8 XCDs (own L2)
+ *              receives a contiguous range of row blocks / column tiles with
+ *              all tasks of each (the default); 0: hardware dispatch order.
+ * The schedule table is process-wide, one entry per (n, precision), read at
+ * every launch (and when a batch captures its graph: a batch re-captures after
+ * any change).  Calls are thread-safe; changing a schedule while another
+ * thread launches the same (n, precision) affects either launch or the next.
+ * ------------------------------------------------------------------------- */
+typedef struct lm_schedule {
+  int32_t col_tile;  /* -1, 0, +1 */
+  int32_t xcd_order; /* 0 or 1 */
+} lm_schedule;
+
+/* The usable schedules of (n, precision), the default first: *count receives
+   their number (at most 6); the first min(cap, count) go to out (out may be
+   null when cap is 0).  Host only. */
+lm_status lm_schedule_candidates(int32_t n, int32_t precision, lm_schedule* out, int32_t cap, int32_t* count);
+
+/* Set / read the schedule of (n, precision).  LM_E_ARG for a schedule that
+   lm_schedule_candidates does not list, LM_E_UNSUPPORTED for other n.  Host only. */
+lm_status lm_set_schedule(int32_t n, int32_t precision, const lm_schedule* s);
+lm_status lm_get_schedule(int32_t n, int32_t precision, lm_schedule* s);
+
+/* Autotune the schedule of the run's (n, precision) on the run itself: every
+   candidate advances a copy of the run's current state by steps RK4 steps
+   (1..64), reps times (1..16), timed with HIP events on the run's stream; the
+   fastest (least of its reps) becomes the table's schedule and is written to
+   *best.  ms (may be null) receives the per-step times of the first cap
+   candidates in lm_schedule_candidates order, *count (may be null) their
+   number.  The run's state, step counters and interval are restored exactly
+   (a device copy of its whole allocation is taken and freed here, so the call
+   needs that much free device memory: LM_E_OOM otherwise).  Synchronous.
+   LM_E_STATE without a state or inside a batch. */
+lm_status lm_autotune(lm_run* run, int32_t steps, int32_t reps, lm_schedule* best, double* ms, int32_t cap,
+                      int32_t* count);
+
 /* ---------------------------------------------------------------------------
  * Two-dimensional incompressible inviscid flow with strategy 1 in two
  * discretisations: the test of the paper's section 4.1 (material conservation
@@ -302,6 +346,7 @@ lm_status lm_e2d_read(lm_e2d* e, int32_t kind, double* out, int on_device);
 /* Release (waits for the stream).  Null is a no-op. */
 lm_status lm_e2d_destroy(lm_e2d* e);
 
+/* Text of a status code (static storage). */
 const char* lm_status_str(lm_status s);
 /* Last error message of the calling thread ("" if none). */
 const char* lm_last_error(void);

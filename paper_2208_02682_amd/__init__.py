@@ -5,7 +5,9 @@ include/lagmean.h.  This package is the thin Python binding (``lagmean``), the
 build script (``build``) and the batch/serving drivers."""
 
 from .lagmean import (LagMeanError, Run, Batch, Euler2D, Config, make_config, footprint, load_library, OUTPUTS, REMAP_OUTPUTS, PEEK,
-                      LM_FIELD_H, LM_FIELD_ZETA)
+                      LM_FIELD_H, LM_FIELD_ZETA, schedule_candidates, set_schedule, get_schedule, save_schedules,
+                      load_schedules)
 
 __all__ = ["LagMeanError", "Run", "Batch", "Euler2D", "Config", "make_config", "footprint", "load_library", "OUTPUTS", "REMAP_OUTPUTS", "PEEK",
-           "LM_FIELD_H", "LM_FIELD_ZETA"]
+           "LM_FIELD_H", "LM_FIELD_ZETA", "schedule_candidates", "set_schedule", "get_schedule", "save_schedules",
+           "load_schedules"]

@@ -1,0 +1,73 @@
+"""Autotuner driver: the launch schedule of every (N, precision) is chosen by
+timing the candidates on the device (lm_autotune, through Run.autotune) and the
+choices are kept in a JSON cache per device architecture.
+
+A schedule is the column-tile width of the column pass and the block order
+(XCD-aware or hardware); every schedule computes the same numbers, so a cache
+changes speed only.  The cache shipped with the package, schedules_gfx950.json,
+holds the choices measured on an MI355X; load_default() applies it.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+from typing import Callable, Iterable, List, Optional, Tuple
+
+from .lagmean import Config, Run, load_schedules, save_schedules
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def cache_path(arch: str) -> str:
+    return os.path.join(HERE, f"schedules_{arch}.json")
+
+
+def device_arch() -> str:
+    """Architecture name of device 0 (e.g. gfx950), from the runtime's properties."""
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def load_default(arch: Optional[str] = None) -> int:
+    """Apply the shipped cache of the device's architecture; returns the number of
+    (N, precision) schedules applied (0 if there is no cache for it)."""
+    arch = arch or device_arch()
+    path = cache_path(arch)
+    if not os.path.exists(path):
+        return 0
+    return load_schedules(path, arch)
+
+
+def tune(specs: Iterable[Tuple[int, str]], config_for: Callable[[int, str], Config],
+         state_for: Callable[[int], tuple], *, warm_steps: int = 20, steps: int = 8, reps: int = 3) -> List[dict]:
+    """Autotune every (N, precision) of specs on a run made with config_for(N,
+    precision) from the state state_for(N), after warm_steps steps of an open
+    interval (so that the strategy-2 gathers reach as far as in a running
+    interval).  Each choice is applied as it is made; returns Run.autotune's
+    records."""
+    out = []
+    for N, prec in specs:
+        with Run(config_for(N, prec)) as r:
+            r.set_state(*state_for(N))
+            r.begin_interval()
+            r.step(warm_steps)
+            out.append(r.autotune(steps, reps))
+    return out
+
+
+def merge_save(path: str, arch: str, tuned: List[dict]) -> None:
+    """Write tuned records to path, keeping the entries of other (N, precision)
+    already there for the same architecture."""
+    keep = []
+    if os.path.exists(path):
+        with open(path) as f:
+            doc = json.load(f)
+        if doc.get("format") == 1 and doc.get("arch") == arch:
+            new = {(t["n"], t["precision"]) for t in tuned}
+            for e in doc["entries"]:
+                if (e["n"], e["precision"]) not in new:
+                    keep.append({"n": e["n"], "precision": e["precision"], "best": (e["col_tile"], e["xcd_order"]),
+                                 "ms": {tuple(int(x) for x in k.split(",")): v for k, v in e["ms_per_step"].items()}})
+    recs = sorted(keep + list(tuned), key=lambda t: (t["n"], t["precision"]))
+    save_schedules(path, arch, recs)

@@ -244,8 +244,9 @@ template <> struct Plan<384, 12>  { static constexpr int R2 = 4,  R3 = 4, R4 = 2
 // measured on the 1024^2 workload it beats 8 values per lane, which halves the
 // registers but needs a barrier per exchange, by about 25% in the row passes),
 // 12 for N = 3 * 2^k (first stage radix 12 = 3 x 4)
+__host__ __device__ constexpr int fft_E_of(int n) { return (n % 3 == 0) ? 12 : 16; }
 template <int N>
-__host__ __device__ constexpr int fft_E() { return (N % 3 == 0) ? 12 : 16; }
+__host__ __device__ constexpr int fft_E() { return fft_E_of(N); }
 
 // exchanges of a transform owned by NT lanes: wavefront-scope ordering when the
 // transform lives in one wavefront, a workgroup barrier otherwise

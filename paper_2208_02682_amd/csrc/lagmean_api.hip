@@ -11,6 +11,7 @@
 #include <type_traits>
 #include <utility>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "lagmean.h"
@@ -57,6 +58,59 @@ lm_status check_cfg(const lm_config* cfg) {
   return LM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// launch schedules, one per (grid size, precision); every launch reads them
+// ---------------------------------------------------------------------------
+std::mutex g_sched_mu;
+lm::Sched g_sched[7][2];  // [size index][fp32]
+unsigned g_sched_gen = 0;  // bumped on every change: batches re-capture their graph
+
+int size_index(int n) {
+  switch (n) {
+    case 64: return 0;
+    case 128: return 1;
+    case 192: return 2;
+    case 256: return 3;
+    case 384: return 4;
+    case 512: return 5;
+    case 1024: return 6;
+  }
+  return -1;
+}
+
+lm::Sched get_sched(int n, bool fp32, unsigned* gen = nullptr) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  if (gen) *gen = g_sched_gen;
+  return g_sched[size_index(n)][fp32 ? 1 : 0];
+}
+
+void put_sched(int n, bool fp32, const lm::Sched& sc) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  g_sched[size_index(n)][fp32 ? 1 : 0] = sc;
+  ++g_sched_gen;
+}
+
+unsigned sched_gen() {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  return g_sched_gen;
+}
+
+// the usable schedules of (n, precision), the default first
+std::vector<lm::Sched> sched_candidates(int n, bool fp32) {
+  std::vector<lm::Sched> out;
+  const int cb = fp32 ? (int)sizeof(cplx<float>) : (int)sizeof(cplx<double>);
+  for (int tile : {0, -1, 1}) {
+    if (!lm::col_tile_usable(n, tile, cb)) continue;
+    for (int remap : {1, 0}) {
+      lm::Sched sc;
+      sc.tile = tile;
+      sc.remap = remap;
+      out.push_back(sc);
+    }
+  }
+  return out;
+}
+
 }  // namespace
 
 struct lm_run : lm::RunView {
@@ -91,9 +145,13 @@ struct lm_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<lm_run*> signature;  // active members the graph was built for
+  unsigned sched_gen = 0;          // schedule table generation the graph was captured with
 };
 
 namespace {
+
+// the launches of a run follow the table's schedule of its (N, precision)
+void use_sched(lm_run* r) { r->sched = get_sched(r->d.N, r->fp32); }
 
 // state field -> (pointer, is_float32)
 std::pair<const void*, int> state_field(lm_run* r, int which) {
@@ -242,6 +300,7 @@ lm_status lm_set_state(lm_run* r, const double* u, const double* v, const double
   LM_DISPATCH_N(r->d.N, lm::launch_io_col_forward, *r, K, 3);
   if ((s = zero_means(r)) != LM_OK) return s;
   r->ys_cur = 0;
+  use_sched(r);
   LM_DISPATCH_N(r->d.N, lm::launch_prologue, *r);
   if ((s = check_launch()) != LM_OK) return s;
   HIP_TRY(hipStreamSynchronize(r->stream));
@@ -284,6 +343,7 @@ lm_status lm_begin_interval(lm_run* r) {
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
   lm_status s;
   if ((s = zero_means(r)) != LM_OK) return s;
+  use_sched(r);
   LM_DISPATCH_N(r->d.N, lm::launch_prologue, *r);
   if ((s = check_launch()) != LM_OK) return s;
   r->n_tau = r->n;
@@ -296,6 +356,7 @@ lm_status lm_step(lm_run* r, int32_t nsteps) {
   if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   if (nsteps < 0) return fail(LM_E_ARG, "nsteps < 0");
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  use_sched(r);
   LM_DISPATCH_N(r->d.N, lm::launch_steps, *r, nsteps);
   return check_launch();
 }
@@ -307,6 +368,7 @@ lm_status lm_step_profiled(lm_run* r, int32_t nsteps, double* ms_avg) {
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
   double ms[3] = {0.0, 0.0, 0.0};
   hipError_t e = hipSuccess;
+  use_sched(r);
   LM_DISPATCH_N_RET(r->d.N, e, lm::launch_steps_profiled, *r, nsteps, ms);
   if (e != hipSuccess) return fail(LM_E_HIP, std::string("profiled step: ") + hipGetErrorString(e));
   lm_status s = check_launch();
@@ -558,13 +620,18 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
     HIP_TRY(hipMemcpy(g.d_desc, bytes.data(), bytes.size(), hipMemcpyHostToDevice));
     launches.push_back({&g, count});
   }
+  std::vector<lm::Sched> scheds;
+  unsigned gen = sched_gen();
+  for (auto& l : launches) scheds.push_back(get_sched(l.g->N, l.g->fp32, &gen));
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   // from here on the capture is always ended, whatever fails
   hipError_t e = hipEventRecord(b->fork_ev, b->stream);
-  for (auto& l : launches) {
+  for (size_t li = 0; li < launches.size(); ++li) {
+    const Launch& l = launches[li];
     if (e == hipSuccess) e = hipStreamWaitEvent(l.g->fork, b->fork_ev, 0);
     if (e == hipSuccess) {
-      LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32, l.g->cubic, l.g->mom);
+      LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32, l.g->cubic, l.g->mom,
+                    scheds[li]);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(l.g->join, l.g->fork);
@@ -587,6 +654,7 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
     return fail(LM_E_HIP, std::string("batch graph: ") + hipGetErrorString(e));
   }
   for (int i : active) b->signature.push_back(b->members[i].run);
+  b->sched_gen = gen;
   return LM_OK;
 }
 
@@ -676,7 +744,7 @@ lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
     for (int i = 0; i < m; ++i)
       if (b->members[i].remaining > 0) active.push_back(i);
     if (active.empty()) break;
-    bool same = b->exec && active.size() == b->signature.size();
+    bool same = b->exec && active.size() == b->signature.size() && b->sched_gen == sched_gen();
     for (size_t j = 0; same && j < active.size(); ++j) same = b->members[active[j]].run == b->signature[j];
     if (!same) {
       lm_status s = batch_rebuild(b, active);
@@ -694,6 +762,115 @@ lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
     for (auto& mm : b->members) a += mm.remaining > 0;
     *active_out = a;
   }
+  return LM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch schedules and the autotuner
+// ---------------------------------------------------------------------------
+
+lm_status lm_schedule_candidates(int32_t n, int32_t precision, lm_schedule* out, int32_t cap, int32_t* count) {
+  if (!supported_n(n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 192, 256, 384, 512 or 1024");
+  if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
+  if (cap < 0 || (cap > 0 && !out)) return fail(LM_E_ARG, "cap < 0 or null out");
+  const std::vector<lm::Sched> c = sched_candidates(n, precision == LM_FP32_MIXED);
+  for (int i = 0; i < (int)c.size() && i < cap; ++i) out[i] = lm_schedule{c[i].tile, c[i].remap};
+  if (count) *count = (int32_t)c.size();
+  return LM_OK;
+}
+
+lm_status lm_set_schedule(int32_t n, int32_t precision, const lm_schedule* s) {
+  if (!supported_n(n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 192, 256, 384, 512 or 1024");
+  if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
+  if (!s) return fail(LM_E_ARG, "null schedule");
+  const bool fp32 = precision == LM_FP32_MIXED;
+  for (const lm::Sched& c : sched_candidates(n, fp32)) {
+    if (c.tile == s->col_tile && c.remap == s->xcd_order) {
+      put_sched(n, fp32, c);
+      return LM_OK;
+    }
+  }
+  return fail(LM_E_ARG, "not a usable schedule for this n and precision");
+}
+
+lm_status lm_get_schedule(int32_t n, int32_t precision, lm_schedule* s) {
+  if (!supported_n(n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 192, 256, 384, 512 or 1024");
+  if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
+  if (!s) return fail(LM_E_ARG, "null schedule");
+  const lm::Sched c = get_sched(n, precision == LM_FP32_MIXED);
+  *s = lm_schedule{c.tile, c.remap};
+  return LM_OK;
+}
+
+lm_status lm_autotune(lm_run* r, int32_t steps, int32_t reps, lm_schedule* best, double* ms, int32_t cap,
+                      int32_t* count) {
+  if (!r) return fail(LM_E_ARG, "null run");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  if (steps < 1 || steps > 64) return fail(LM_E_ARG, "steps must be in 1..64");
+  if (reps < 1 || reps > 16) return fail(LM_E_ARG, "reps must be in 1..16");
+  if (cap < 0 || (cap > 0 && !ms)) return fail(LM_E_ARG, "cap < 0 or null ms");
+  const std::vector<lm::Sched> cand = sched_candidates(r->d.N, r->fp32);
+  const size_t bytes = r->L.total;
+  void* snap = nullptr;
+  if (hipMalloc(&snap, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LM_E_OOM, "autotune: no room for a copy of the run");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int64_t n0 = r->n, nt0 = r->n_tau;
+  const int ys0 = r->ys_cur;
+  const lm::Sched keep = r->sched;
+  std::vector<double> best_ms(cand.size(), 0.0);
+  // every exit below restores the run and frees the copy
+  hipError_t e = hipMemcpyAsync(snap, r->slab, bytes, hipMemcpyDeviceToDevice, r->stream);
+  const bool have_copy = (e == hipSuccess);
+  auto restore = [&]() -> hipError_t {
+    r->n = n0;
+    r->n_tau = nt0;
+    r->ys_cur = ys0;
+    r->sched = keep;
+    return have_copy ? hipMemcpyAsync(r->slab, snap, bytes, hipMemcpyDeviceToDevice, r->stream) : hipSuccess;
+  };
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  // one untimed step first: caches and clocks in their working state
+  if (e == hipSuccess) {
+    LM_DISPATCH_N(r->d.N, lm::launch_steps, *r, 1);
+    e = hipGetLastError();
+  }
+  for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
+    double bk = 0.0;
+    for (int rep = 0; rep < reps && e == hipSuccess; ++rep) {
+      e = restore();
+      r->sched = cand[k];
+      if (e == hipSuccess) e = hipEventRecord(e0, r->stream);
+      if (e == hipSuccess) {
+        LM_DISPATCH_N(r->d.N, lm::launch_steps, *r, steps);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, r->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e == hipSuccess && (rep == 0 || t < bk)) bk = t;
+    }
+    best_ms[k] = bk / steps;
+  }
+  const hipError_t er = restore();
+  const hipError_t es = hipStreamSynchronize(r->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(snap);
+  if (e == hipSuccess) e = (er != hipSuccess) ? er : es;
+  if (e != hipSuccess) return fail(LM_E_HIP, std::string("autotune: ") + hipGetErrorString(e));
+  size_t bi = 0;
+  for (size_t k = 1; k < cand.size(); ++k)
+    if (best_ms[k] < best_ms[bi]) bi = k;
+  put_sched(r->d.N, r->fp32, cand[bi]);
+  if (best) *best = lm_schedule{cand[bi].tile, cand[bi].remap};
+  for (int k = 0; k < (int)cand.size() && k < cap; ++k) ms[k] = best_ms[k];
+  if (count) *count = (int32_t)cand.size();
   return LM_OK;
 }
 

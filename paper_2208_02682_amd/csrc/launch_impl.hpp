@@ -18,14 +18,28 @@ template <int N>
 dim3 row_grid(int tasks) {
   return dim3(N / RowGeo<N>::RPB, tasks);
 }
-template <int N>
+template <int N, int W = 0>
 dim3 col_grid(const Dims& d, int groups) {
-  constexpr int C = col_tile<N>();
+  constexpr int C = col_tile<N, W>();
   return dim3((d.NKX + C - 1) / C, groups);
 }
-template <int N>
+template <int N, int W = 0>
 dim3 col_block() {
-  return dim3(col_threads<N>());
+  return dim3(col_threads<N, W>());
+}
+
+// calls go(std::integral_constant<int, W>) with the schedule's tile width W
+// (the default width if that one is not usable for this N and precision)
+template <typename T, int N, typename F>
+void with_tile(int tile, F&& go) {
+  constexpr int cb = (int)sizeof(cplx<T>);
+  if constexpr (col_tile_usable(N, -1, cb)) {
+    if (tile < 0) return go(std::integral_constant<int, -1>{});
+  }
+  if constexpr (col_tile_usable(N, 1, cb)) {
+    if (tile > 0) return go(std::integral_constant<int, 1>{});
+  }
+  go(std::integral_constant<int, 0>{});
 }
 
 template <typename T, int N>
@@ -34,9 +48,12 @@ void launch_columns_t(RunView& r, int stage) {
   cplx<T>* Ys[2] = {(cplx<T>*)r.at(r.L.Ys0), (cplx<T>*)r.at(r.L.Ys1)};
   const cplx<T>* Ys_in = Ys[r.ys_cur];
   cplx<T>* Ys_out = (stage < 0) ? Ys[r.ys_cur] : Ys[r.ys_cur ^ 1];
-  hipLaunchKernelGGL((k_columns<T, N>), col_grid<N>(r.d, r.mom ? NCG_MOM : NCG), col_block<N>(), 0, r.stream, P,
-                     r.d, r.ph, stage,
-                     Ys_in, Ys_out);
+  const int groups = r.mom ? NCG_MOM : NCG;
+  with_tile<T, N>(r.sched.tile, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    const dim3 g = col_grid<N, W>(r.d, groups), b = col_block<N, W>();
+    hipLaunchKernelGGL((k_columns<T, N, W>), g, b, 0, r.stream, P, r.d, r.ph, stage, Ys_in, Ys_out, r.sched.remap);
+  });
   if (stage >= 0) r.ys_cur ^= 1;
 }
 
@@ -44,12 +61,13 @@ void launch_columns_t(RunView& r, int stage) {
 template <typename T, int N>
 void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
   const dim3 g = row_grid<N>(NRT), b(64 * ROW_WAVES);
-  if (r.cubic) hipLaunchKernelGGL((k_rows_rhs<T, N, true>), g, b, 0, r.stream, P, r.d, sval);
-  else hipLaunchKernelGGL((k_rows_rhs<T, N, false>), g, b, 0, r.stream, P, r.d, sval);
+  const int rm = r.sched.remap;
+  if (r.cubic) hipLaunchKernelGGL((k_rows_rhs<T, N, true>), g, b, 0, r.stream, P, r.d, sval, rm);
+  else hipLaunchKernelGGL((k_rows_rhs<T, N, false>), g, b, 0, r.stream, P, r.d, sval, rm);
   if (r.mom) {
     const dim3 gm = row_grid<N>(2);
-    if (r.cubic) hipLaunchKernelGGL((k_rows_mom<T, N, true>), gm, b, 0, r.stream, P, r.d, sval);
-    else hipLaunchKernelGGL((k_rows_mom<T, N, false>), gm, b, 0, r.stream, P, r.d, sval);
+    if (r.cubic) hipLaunchKernelGGL((k_rows_mom<T, N, true>), gm, b, 0, r.stream, P, r.d, sval, rm);
+    else hipLaunchKernelGGL((k_rows_mom<T, N, false>), gm, b, 0, r.stream, P, r.d, sval, rm);
   }
 }
 
@@ -61,7 +79,8 @@ void launch_steps_t(RunView& r, int nsteps) {
     for (int stage = 0; stage < 4; ++stage) {
       // time since the interval start, from integers
       const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d);
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
+                         r.sched.remap);
       launch_rows_rhs<T, N>(r, P, sval);
       launch_columns_t<T, N>(r, stage);
     }
@@ -95,7 +114,8 @@ hipError_t launch_steps_profiled_t(RunView& r, int nsteps, double* ms) {
       // start marker absorbs the work done at kernel boundaries, so each
       // interval covers one kernel's execution only
       (void)hipEventRecord(ev[e++], r.stream);
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d);
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
+                         r.sched.remap);
       (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
       (void)hipEventRecord(ev[e++], r.stream);
@@ -128,33 +148,39 @@ hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms) {
 // one RK4 step of every run of one (N, precision) group: blockIdx.z selects
 // the run's descriptor
 template <typename T, int N>
-void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool cubic, bool mom) {
+void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool cubic, bool mom, const Sched& sc) {
   const Dims d = Dims::make(N);
+  const int rm = sc.remap;
   for (int stage = 0; stage < 4; ++stage) {
     dim3 g1 = row_grid<N>(1);
     g1.z = nruns;
-    hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, dim3(64 * ROW_WAVES), 0, st, desc);
+    hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, dim3(64 * ROW_WAVES), 0, st, desc, rm);
     dim3 g2 = row_grid<N>(NRT);
     g2.z = nruns;
     const dim3 b2(64 * ROW_WAVES);
-    if (cubic) hipLaunchKernelGGL((k_rows_rhs_b<T, N, true>), g2, b2, 0, st, desc, stage);
-    else hipLaunchKernelGGL((k_rows_rhs_b<T, N, false>), g2, b2, 0, st, desc, stage);
+    if (cubic) hipLaunchKernelGGL((k_rows_rhs_b<T, N, true>), g2, b2, 0, st, desc, stage, rm);
+    else hipLaunchKernelGGL((k_rows_rhs_b<T, N, false>), g2, b2, 0, st, desc, stage, rm);
     if (mom) {
       dim3 gm = row_grid<N>(2);
       gm.z = nruns;
-      if (cubic) hipLaunchKernelGGL((k_rows_mom_b<T, N, true>), gm, b2, 0, st, desc, stage);
-      else hipLaunchKernelGGL((k_rows_mom_b<T, N, false>), gm, b2, 0, st, desc, stage);
+      if (cubic) hipLaunchKernelGGL((k_rows_mom_b<T, N, true>), gm, b2, 0, st, desc, stage, rm);
+      else hipLaunchKernelGGL((k_rows_mom_b<T, N, false>), gm, b2, 0, st, desc, stage, rm);
     }
-    dim3 g3 = col_grid<N>(d, mom ? NCG_MOM : NCG);
-    g3.z = nruns;
-    hipLaunchKernelGGL((k_columns_b<T, N>), g3, col_block<N>(), 0, st, desc, stage);
+    with_tile<T, N>(sc.tile, [&](auto w) {
+      constexpr int W = decltype(w)::value;
+      dim3 g3 = col_grid<N, W>(d, mom ? NCG_MOM : NCG);
+      g3.z = nruns;
+      const dim3 b3 = col_block<N, W>();
+      hipLaunchKernelGGL((k_columns_b<T, N, W>), g3, b3, 0, st, desc, stage, rm);
+    });
   }
 }
 
 template <int N>
-void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic, bool mom) {
-  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns, cubic, mom);
-  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns, cubic, mom);
+void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic, bool mom,
+                       const Sched& sc) {
+  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns, cubic, mom, sc);
+  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns, cubic, mom, sc);
 }
 
 template <int N>
@@ -192,14 +218,36 @@ void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
 
 }  // namespace lm
 
-#define LM_INSTANTIATE(N)                                                                \
-  namespace lm {                                                                         \
-  template void launch_steps<N>(RunView&, int);                                          \
-  template void launch_batch_step<N>(hipStream_t, const void*, int, bool, bool, bool);   \
-  template hipError_t launch_steps_profiled<N>(RunView&, int, double*);                  \
-  template void launch_prologue<N>(RunView&);                                            \
-  template void launch_io_row_forward<N>(RunView&, const IoRowFwd&, int);                \
-  template void launch_io_col_forward<N>(RunView&, const IoColFwd&, int);                \
-  template void launch_io_col_inverse<N>(RunView&, const IoColInv&, int);                \
-  template void launch_io_row_inverse<N>(RunView&, const IoRowInv&, int);                \
+// The per-precision step launchers (and with them every time-stepping kernel)
+// are instantiated in inst_<N>_f32.hip and inst_<N>_f64.hip, the dispatchers
+// and the float64 boundary launchers in inst_<N>.hip: three translation units
+// per grid size compile in parallel.
+#define LM_INSTANTIATE_T(T, N)                                                                           \
+  namespace lm {                                                                                         \
+  template void launch_steps_t<T, N>(RunView&, int);                                                     \
+  template hipError_t launch_steps_profiled_t<T, N>(RunView&, int, double*);                             \
+  template void launch_columns_t<T, N>(RunView&, int);                                                   \
+  template void launch_batch_step_t<T, N>(hipStream_t, const RunDesc<T>*, int, bool, bool, const Sched&); \
+  }
+
+#define LM_EXTERN_T(T, N)                                                                                       \
+  namespace lm {                                                                                                \
+  extern template void launch_steps_t<T, N>(RunView&, int);                                                     \
+  extern template hipError_t launch_steps_profiled_t<T, N>(RunView&, int, double*);                             \
+  extern template void launch_columns_t<T, N>(RunView&, int);                                                   \
+  extern template void launch_batch_step_t<T, N>(hipStream_t, const RunDesc<T>*, int, bool, bool, const Sched&); \
+  }
+
+#define LM_INSTANTIATE(N)                                                                             \
+  LM_EXTERN_T(float, N)                                                                               \
+  LM_EXTERN_T(double, N)                                                                              \
+  namespace lm {                                                                                      \
+  template void launch_steps<N>(RunView&, int);                                                       \
+  template void launch_batch_step<N>(hipStream_t, const void*, int, bool, bool, bool, const Sched&);  \
+  template hipError_t launch_steps_profiled<N>(RunView&, int, double*);                               \
+  template void launch_prologue<N>(RunView&);                                                         \
+  template void launch_io_row_forward<N>(RunView&, const IoRowFwd&, int);                             \
+  template void launch_io_col_forward<N>(RunView&, const IoColFwd&, int);                             \
+  template void launch_io_col_inverse<N>(RunView&, const IoColInv&, int);                             \
+  template void launch_io_row_inverse<N>(RunView&, const IoRowInv&, int);                             \
   }

@@ -9,6 +9,7 @@
 
 #include <type_traits>
 
+#include "col_tile.hpp"
 #include "fft_core.hpp"
 #include "layout.hpp"
 #include "step_args.hpp"
@@ -64,6 +65,14 @@ inline Layout make_layout(const Dims& d, bool fp32, bool mom) {
   return L;
 }
 
+// Launch schedule of the time-stepping kernels of one (N, precision): the
+// column tile width (col_tile_of) and the block order (xcd_split).  Neither
+// changes what a row or a column computes, or in which order.
+struct Sched {
+  int tile = 0;   // -1: half the default column tile width, 0: default, +1: twice
+  int remap = 1;  // 1: XCD-aware block order, 0: hardware order
+};
+
 struct RunView {
   Dims d;
   Phys ph;
@@ -75,6 +84,7 @@ struct RunView {
   char* slab;
   int64_t n, n_tau;  // steps since set_state; step index at the interval start
   int ys_cur;        // which stage-value buffer holds the current stage input
+  Sched sched;       // launch schedule used by the next launches
   void* at(size_t off) const { return slab + off; }
 };
 

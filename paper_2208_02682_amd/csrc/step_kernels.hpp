@@ -33,6 +33,7 @@
 #include <type_traits>
 
 #include "fft_core.hpp"
+#include "col_tile.hpp"
 #include "layout.hpp"
 #include "step_args.hpp"
 
@@ -56,15 +57,10 @@ __device__ __forceinline__ int row_group() {
   else return threadIdx.x / NT;
 }
 
-// column tile width: 8 columns (64-byte row segments in float32), or more when a
-// transform needs fewer than 8 lanes, so that a block is at least one wavefront
-template <int N>
-__host__ __device__ constexpr int col_tile() {
-  return (N / fft_E<N>() >= 8) ? 8 : 64 / (N / fft_E<N>());
-}
-template <int N>
-__host__ __device__ constexpr int col_threads() { return col_tile<N>() * (N / fft_E<N>()); }
-__host__ __device__ constexpr int col_buf(int N) { return padded_len(N) | 1; }
+template <int N, int W = 0>
+__host__ __device__ constexpr int col_tile() { return col_tile_of(N, W); }
+template <int N, int W = 0>
+__host__ __device__ constexpr int col_threads() { return col_tile<N, W>() * (N / fft_E<N>()); }
 
 // --------------------------------------------------------------------------
 // row helpers
@@ -148,12 +144,13 @@ __device__ __forceinline__ int wrap2N(int i) {
 // all tasks of neighbouring rows / column tiles meet in the same L2 (the
 // gathers, re-read rows and shared 128-byte lines hit in L2).
 constexpr int NUM_XCD = 8;
-__device__ __forceinline__ void xcd_split(int nslow, int nfast, int& slow, int& fast, int& z) {
+// remap = 0 keeps the hardware order (logical index = flattened block index).
+__device__ __forceinline__ void xcd_split(int nslow, int nfast, int& slow, int& fast, int& z, int remap) {
   const int total = nslow * nfast * gridDim.z;
   const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const int q = total / NUM_XCD, r = total % NUM_XCD;
   const int xcd = b % NUM_XCD;
-  const int logical = xcd * q + min(xcd, r) + b / NUM_XCD;
+  const int logical = remap ? xcd * q + min(xcd, r) + b / NUM_XCD : b;
   fast = logical % nfast;
   const int rest = logical / nfast;
   slow = rest % nslow;
@@ -317,10 +314,10 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d) {
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d, int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, unused, z;
-  xcd_split(gridDim.x, 1, rowblock, unused, z);
+  xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
   rows_dyn_body<T, N>(P, d, rowblock, lds);
 }
 
@@ -467,10 +464,10 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
 
 // CUB: cubic instead of bilinear strategy-2 gathers
 template <typename T, int N, bool CUB>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s) {
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s, int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, task, z;
-  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);  // grid = (row blocks, tasks)
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);  // grid = (row blocks, tasks)
   rows_rhs_body<T, N, CUB>(P, d, s, rowblock, task, lds);
 }
 
@@ -558,10 +555,10 @@ __device__ __forceinline__ void rows_mom_body(const StepPtrs<T>& P, const Dims& 
 }
 
 template <typename T, int N, bool CUB>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom(StepPtrs<T> P, Dims d, double s) {
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom(StepPtrs<T> P, Dims d, double s, int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, task, z;
-  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);  // grid = (row blocks, 2 components)
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);  // grid = (row blocks, 2 components)
   rows_mom_body<T, N, CUB>(P, d, s, rowblock, task, lds);
 }
 
@@ -802,11 +799,10 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
 }
 
 // stage >= 0: RK4 stage; stage < 0: only transform the current state (prologue)
-template <typename T, int N>
+template <typename T, int N, int C>
 __device__ __forceinline__ void columns_body(const StepPtrs<T>& P, const Dims& d, const Phys& ph, int stage,
                                              const cplx<T>* Ys_in, cplx<T>* Ys_out, int tile, int group,
                                              cplx<T>* lds) {
-  constexpr int C = col_tile<N>();
   constexpr int E = fft_E<N>(), NT = N / E, LC = col_buf(N);
   ColCtx<T, N, C> cx;
   cx.lds = lds;
@@ -842,13 +838,14 @@ __host__ __device__ constexpr int col_waves() {
   return (sizeof(T) == 4 && N != 512 && !(BATCHED && N == 1024)) ? 4 : 1;
 }
 
-template <typename T, int N>
-__global__ void __launch_bounds__(col_threads<N>(), (col_waves<T, N, false>()))
-    k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out) {
-  __shared__ cplx<T> lds[col_tile<N>() * col_buf(N)];
+// W: column tile width (col_tile<N, W>)
+template <typename T, int N, int W>
+__global__ void __launch_bounds__((col_threads<N, W>()), (col_waves<T, N, false>()))
+    k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out, int remap) {
+  __shared__ cplx<T> lds[col_tile<N, W>() * col_buf(N)];
   int tile, group, z;
-  xcd_split(gridDim.x, gridDim.y, tile, group, z);  // grid = (column tiles, field groups)
-  columns_body<T, N>(P, d, ph, stage, Ys_in, Ys_out, tile, group, lds);
+  xcd_split(gridDim.x, gridDim.y, tile, group, z, remap);  // grid = (column tiles, field groups)
+  columns_body<T, N, col_tile<N, W>()>(P, d, ph, stage, Ys_in, Ys_out, tile, group, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -856,18 +853,18 @@ __global__ void __launch_bounds__(col_threads<N>(), (col_waves<T, N, false>()))
 // --------------------------------------------------------------------------
 
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn_b(const RunDesc<T>* __restrict__ runs) {
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn_b(const RunDesc<T>* __restrict__ runs, int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, unused, z;
-  xcd_split(gridDim.x, 1, rowblock, unused, z);
+  xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
   rows_dyn_body<T, N>(runs[z].P, Dims::make(N), rowblock, lds);
 }
 
 template <typename T, int N, bool CUB>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>* __restrict__ runs, int stage) {
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>* __restrict__ runs, int stage, int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, task, z;
-  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);
   const RunDesc<T>& R = runs[z];
   // time since the interval start, from integers (as the single-run path)
   const double c = (stage == 0) ? 0.0 : ((stage == 3) ? 1.0 : 0.5);
@@ -876,10 +873,10 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>*
 }
 
 template <typename T, int N, bool CUB>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom_b(const RunDesc<T>* __restrict__ runs, int stage) {
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom_b(const RunDesc<T>* __restrict__ runs, int stage, int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, task, z;
-  xcd_split(gridDim.x, gridDim.y, rowblock, task, z);
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);
   const RunDesc<T>& R = runs[z];
   const double c = (stage == 0) ? 0.0 : ((stage == 3) ? 1.0 : 0.5);
   const double s = (double(*R.counter) + c) * R.ph.dt;
@@ -888,15 +885,16 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom_b(const RunDesc<T>*
 
 // stage parity selects the stage-value buffers: between steps the current
 // stage input is always Ys0 (four swaps per step)
-template <typename T, int N>
-__global__ void __launch_bounds__(col_threads<N>(), (col_waves<T, N, true>())) k_columns_b(const RunDesc<T>* __restrict__ runs, int stage) {
-  __shared__ cplx<T> lds[col_tile<N>() * col_buf(N)];
+template <typename T, int N, int W>
+__global__ void __launch_bounds__((col_threads<N, W>()), (col_waves<T, N, true>()))
+    k_columns_b(const RunDesc<T>* __restrict__ runs, int stage, int remap) {
+  __shared__ cplx<T> lds[col_tile<N, W>() * col_buf(N)];
   int tile, group, z;
-  xcd_split(gridDim.x, gridDim.y, tile, group, z);
+  xcd_split(gridDim.x, gridDim.y, tile, group, z, remap);
   const RunDesc<T>& R = runs[z];
   const cplx<T>* Ys_in = (stage & 1) ? R.Ys1 : R.Ys0;
   cplx<T>* Ys_out = (stage & 1) ? R.Ys0 : R.Ys1;
-  columns_body<T, N>(R.P, Dims::make(N), R.ph, stage, Ys_in, Ys_out, tile, group, lds);
+  columns_body<T, N, col_tile<N, W>()>(R.P, Dims::make(N), R.ph, stage, Ys_in, Ys_out, tile, group, lds);
 }
 
 }  // namespace lm

@@ -9,8 +9,9 @@ has not been built.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
-from typing import Dict, Optional
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -63,6 +64,14 @@ class E2DConfig(ctypes.Structure):
                 ("interp", ctypes.c_int32)]
 
 
+class Schedule(ctypes.Structure):
+    """lm_schedule: column tile width (-1, 0, +1) and XCD-aware block order (0, 1)."""
+    _fields_ = [("col_tile", ctypes.c_int32), ("xcd_order", ctypes.c_int32)]
+
+    def key(self) -> Tuple[int, int]:
+        return (int(self.col_tile), int(self.xcd_order))
+
+
 E2D_OUTPUTS = {"zeta": 0, "PS_mean": 1, "PS_eta_x": 2, "PS_eta_y": 3, "SL_mean": 4, "SL_eta_x": 5, "SL_eta_y": 6}
 
 _lib: Optional[ctypes.CDLL] = None
@@ -97,6 +106,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_batch_step": [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
         "lm_batch_remaining": [P, P, ctypes.POINTER(ctypes.c_int32)],
         "lm_batch_destroy": [P],
+        "lm_schedule_candidates": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)],
+        "lm_set_schedule": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule)],
+        "lm_get_schedule": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule)],
+        "lm_autotune": [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule), D, ctypes.c_int32,
+                        ctypes.POINTER(ctypes.c_int32)],
         "lm_e2d_create": [ctypes.POINTER(E2DConfig), P, ctypes.POINTER(P)],
         "lm_e2d_set_vorticity": [P, P, ctypes.c_int],
         "lm_e2d_begin_interval": [P],
@@ -133,6 +148,56 @@ def make_config(n: int, *, precision: str = "fp64", f: float = 1.0, g: float = 1
     fields = (LM_F_H | LM_F_ZETA | LM_F_MOMENTUM) if momentum else 0
     return Config(n=n, precision=prec, f=f, g=g, H=H, dt=dt, nu8=nu8, avg_fields=fields, strategies=0,
                   interp=LM_INTERP[interp], mode=0)
+
+
+PRECISIONS = {"fp64": LM_FP64, "fp32": LM_FP32_MIXED}
+
+
+def schedule_candidates(n: int, precision: str) -> List[Tuple[int, int]]:
+    """Usable launch schedules (col_tile, xcd_order) of (n, precision), the default first."""
+    lib = load_library()
+    buf = (Schedule * 8)()
+    cnt = ctypes.c_int32(0)
+    _check(lib.lm_schedule_candidates(n, PRECISIONS[precision], buf, 8, ctypes.byref(cnt)))
+    return [buf[i].key() for i in range(cnt.value)]
+
+
+def set_schedule(n: int, precision: str, col_tile: int, xcd_order: int) -> None:
+    s = Schedule(col_tile=col_tile, xcd_order=xcd_order)
+    _check(load_library().lm_set_schedule(n, PRECISIONS[precision], ctypes.byref(s)))
+
+
+def get_schedule(n: int, precision: str) -> Tuple[int, int]:
+    s = Schedule()
+    _check(load_library().lm_get_schedule(n, PRECISIONS[precision], ctypes.byref(s)))
+    return s.key()
+
+
+def save_schedules(path: str, arch: str, tuned: List[dict]) -> None:
+    """Write autotuning results as JSON: arch (the device's architecture name)
+    and one entry per (n, precision) with the chosen schedule and the per-step
+    times of every candidate (as returned by Run.autotune)."""
+    entries = []
+    for t in tuned:
+        entries.append({"n": int(t["n"]), "precision": t["precision"], "col_tile": int(t["best"][0]),
+                        "xcd_order": int(t["best"][1]),
+                        "ms_per_step": {f"{k[0]},{k[1]}": float(v) for k, v in t["ms"].items()}})
+    with open(path, "w") as f:
+        json.dump({"format": 1, "arch": arch, "entries": entries}, f, indent=1)
+
+
+def load_schedules(path: str, arch: Optional[str] = None) -> int:
+    """Apply the schedules of a JSON cache written by save_schedules (only if
+    its arch matches, when arch is given); returns the number applied."""
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("format") != 1:
+        raise ValueError(f"{path}: unknown schedule cache format")
+    if arch is not None and doc.get("arch") != arch:
+        return 0
+    for e in doc["entries"]:
+        set_schedule(int(e["n"]), e["precision"], int(e["col_tile"]), int(e["xcd_order"]))
+    return len(doc["entries"])
 
 
 def footprint(cfg: Config) -> int:
@@ -241,6 +306,20 @@ class Run:
 
     def remap_outputs(self) -> Dict[str, np.ndarray]:
         return {name: self.read_mean(fk[0], fk[1]) for name, fk in REMAP_OUTPUTS.items()}
+
+    def autotune(self, steps: int = 8, reps: int = 3) -> dict:
+        """Time every launch schedule of this run's (N, precision) on a copy of
+        its state (lm_autotune; the run itself is left as it was) and make the
+        fastest the schedule of that (N, precision).  Returns {"n", "precision",
+        "best": (col_tile, xcd_order), "ms": {schedule: ms per step}}."""
+        cand = schedule_candidates(self.N, "fp32" if self.cfg.precision == LM_FP32_MIXED else "fp64")
+        ms = (ctypes.c_double * len(cand))()
+        best = Schedule()
+        cnt = ctypes.c_int32(0)
+        _check(self.lib.lm_autotune(self.h, int(steps), int(reps), ctypes.byref(best), ms, len(cand),
+                                    ctypes.byref(cnt)))
+        return {"n": self.N, "precision": "fp32" if self.cfg.precision == LM_FP32_MIXED else "fp64",
+                "best": best.key(), "ms": {cand[i]: ms[i] for i in range(cnt.value)}}
 
     def peek(self, which: str):
         out = np.empty((self.N, self.N))
