@@ -162,6 +162,27 @@ def apply_schedules(a, specs, config_for, state_for) -> str:
     return source
 
 
+def tune_batched(a, ws, states):
+    """With --autotune: the batched launches' schedules, measured on a batch of
+    the given runs (lm_batch_autotune), saved to --schedules-out if given."""
+    if not a.autotune:
+        return
+    from paper_2208_02682_amd import Run
+    from paper_2208_02682_amd import autotune as at
+    runs = [Run(_cfg(w)) for w in ws]
+    try:
+        for r, st in zip(runs, states):
+            r.set_state(*st)
+        tuned = at.tune_batch(runs)
+    finally:
+        for r in runs:
+            r.close()
+    for t in tuned:
+        print(f"autotune (batched): N={t['n']} {t['precision']}: {t['best']}", file=sys.stderr, flush=True)
+    if a.schedules_out:
+        at.merge_save(a.schedules_out, at.device_arch(), tuned)
+
+
 def bench_tune(a) -> dict:
     """The autotuner over every grid size and precision; writes the cache."""
     import torch
@@ -177,10 +198,16 @@ def bench_tune(a) -> dict:
         a.schedules_out = at.cache_path(at.device_arch())
     t0 = time.perf_counter()
     apply_schedules(a, specs, lambda N, p: _cfg(ws[N], p), lambda N: states[N])
+    # the batched launches: the 64 uneven runs of the batched workload
+    from synth.workloads import batch_workloads
+    bws = batch_workloads(a.batch_runs)
+    tune_batched(a, bws, generate_states(bws))
     from paper_2208_02682_amd import get_schedule
     return {"mode": "tune", "arch": at.device_arch(), "seconds": time.perf_counter() - t0,
             "cache": os.path.relpath(a.schedules_out, ROOT),
-            "schedules": {f"{N}:{p}": list(get_schedule(N, p)) for N, p in specs}}
+            "schedules": {f"{N}:{p}": list(get_schedule(N, p)) for N, p in specs},
+            "batched_schedules": {f"{N}:fp32": list(get_schedule(N, "fp32", batched=True))
+                                  for N in sorted({w.N for w in bws})}}
 
 
 def bench_batch(a) -> dict:
@@ -200,6 +227,7 @@ def bench_batch(a) -> dict:
     sizes = sorted(first)
     source = apply_schedules(a, [(N, p) for N in sizes for p in ("fp32", "fp64")],
                              lambda N, p: _cfg(first[N][0], p), lambda N: first[N][1])
+    tune_batched(a, ws, states)
     from paper_2208_02682_amd import get_schedule
 
     def start(run, st):
@@ -270,6 +298,7 @@ def bench_batch(a) -> dict:
                    "runs": len(ws), "total_steps": sum(w.steps_per_interval for w in ws),
                    "grid_point_steps": pts, "tick_steps": a.tick_steps,
                    "schedules": {f"{N}:{p}": list(get_schedule(N, p)) for N in sizes for p in ("fp32", "fp64")},
+                   "batched_schedules": {f"{N}:fp32": list(get_schedule(N, "fp32", batched=True)) for N in sizes},
                    "schedule_source": source},
         "seconds": {"batched": t_batch, "alone_sequential": t_alone, "fp64_alone_sequential": t_fp64},
         "alone_sequential_value": pts / t_alone, "fp64_alone_sequential_value": pts / t_fp64,

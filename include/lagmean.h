@@ -257,10 +257,13 @@ lm_status lm_batch_destroy(lm_batch* b);
  *   xcd_order  1: blocks renumbered so that each of the 8 XCDs (own L2)
  *              receives a contiguous range of row blocks / column tiles with
  *              all tasks of each (the default); 0: hardware dispatch order.
- * The schedule table is process-wide, one entry per (n, precision), read at
- * every launch (and when a batch captures its graph: a batch re-captures after
- * any change).  Calls are thread-safe; changing a schedule while another
- * thread launches the same (n, precision) affects either launch or the next.
+ * Two process-wide schedule tables, one entry per (n, precision) each: one for
+ * single runs, read at every launch, and one for batched launches, read when a
+ * batch captures its graph (a batch re-captures after any change of either
+ * table).  The best schedule differs between the two (a single run of a small
+ * grid wants more, narrower blocks; a batch fills the GPU with its runs).
+ * Calls are thread-safe; changing a schedule while another thread launches the
+ * same (n, precision) affects either launch or the next.
  * ------------------------------------------------------------------------- */
 typedef struct lm_schedule {
   int32_t col_tile;  /* -1, 0, +1 */
@@ -276,6 +279,9 @@ lm_status lm_schedule_candidates(int32_t n, int32_t precision, lm_schedule* out,
    lm_schedule_candidates does not list, LM_E_UNSUPPORTED for other n.  Host only. */
 lm_status lm_set_schedule(int32_t n, int32_t precision, const lm_schedule* s);
 lm_status lm_get_schedule(int32_t n, int32_t precision, lm_schedule* s);
+/* The same for the batched launches' table. */
+lm_status lm_set_batch_schedule(int32_t n, int32_t precision, const lm_schedule* s);
+lm_status lm_get_batch_schedule(int32_t n, int32_t precision, lm_schedule* s);
 
 /* Autotune the schedule of the run's (n, precision) on the run itself: every
    candidate advances a copy of the run's current state by steps RK4 steps
@@ -289,6 +295,16 @@ lm_status lm_get_schedule(int32_t n, int32_t precision, lm_schedule* s);
    LM_E_STATE without a state or inside a batch. */
 lm_status lm_autotune(lm_run* run, int32_t steps, int32_t reps, lm_schedule* best, double* ms, int32_t cap,
                       int32_t* count);
+
+/* Autotune the batched launches' schedules on a batch's members: for each
+   (n, precision) present in turn (the others at their current schedule), every
+   candidate is installed, the batch graph captured and steps (1..64) graph
+   launches of all members timed, reps times (1..16); the fastest stays in the
+   batched table.  Every member's allocation and counters are restored exactly
+   (copies of all members' allocations are taken and freed here: LM_E_OOM if
+   they do not fit).  Budgets are untouched.  *tuned (may be null) receives the
+   number of (n, precision) tuned.  Synchronous. */
+lm_status lm_batch_autotune(lm_batch* b, int32_t steps, int32_t reps, int32_t* tuned);
 
 /* ---------------------------------------------------------------------------
  * Two-dimensional incompressible inviscid flow with strategy 1 in two

@@ -4,7 +4,9 @@ choices are kept in a JSON cache per device architecture.
 
 A schedule is the column-tile width of the column pass and the block order
 (XCD-aware or hardware); every schedule computes the same numbers, so a cache
-changes speed only.  The cache shipped with the package, schedules_gfx950.json,
+changes speed only.  Single runs and batched launches have separate tables
+(tune: single runs, one at a time; tune_batch: the batched launches, on a
+batch of runs).  The cache shipped with the package, schedules_gfx950.json,
 holds the choices measured on an MI355X; load_default() applies it.
 """
 
@@ -56,18 +58,39 @@ def tune(specs: Iterable[Tuple[int, str]], config_for: Callable[[int, str], Conf
     return out
 
 
+def tune_batch(runs: List[Run], *, warm_steps: int = 20, steps: int = 4, reps: int = 3) -> List[dict]:
+    """Autotune the batched launches' schedules on runs (each with a state; an
+    interval is opened here and warm_steps steps taken first): they join one
+    batch, lm_batch_autotune tunes every (N, precision) among them, and the
+    batch is released.  The runs keep their state, with the interval open."""
+    from .lagmean import Batch
+    for r in runs:
+        r.begin_interval()
+        r.step(warm_steps)
+    with Batch() as b:
+        for r in runs:
+            b.add(r, 1)
+        out = b.autotune(steps, reps)
+        for r in runs:
+            b.remove(r)
+    return out
+
+
 def merge_save(path: str, arch: str, tuned: List[dict]) -> None:
-    """Write tuned records to path, keeping the entries of other (N, precision)
-    already there for the same architecture."""
+    """Write tuned records to path, keeping the entries of other (context, N,
+    precision) already there for the same architecture."""
+    def key(t):
+        return (t.get("context", "single"), t["n"], t["precision"])
     keep = []
     if os.path.exists(path):
         with open(path) as f:
             doc = json.load(f)
         if doc.get("format") == 1 and doc.get("arch") == arch:
-            new = {(t["n"], t["precision"]) for t in tuned}
+            new = {key(t) for t in tuned}
             for e in doc["entries"]:
-                if (e["n"], e["precision"]) not in new:
-                    keep.append({"n": e["n"], "precision": e["precision"], "best": (e["col_tile"], e["xcd_order"]),
+                if key(e) not in new:
+                    keep.append({"context": e.get("context", "single"), "n": e["n"], "precision": e["precision"],
+                                 "best": (e["col_tile"], e["xcd_order"]),
                                  "ms": {tuple(int(x) for x in k.split(",")): v for k, v in e["ms_per_step"].items()}})
-    recs = sorted(keep + list(tuned), key=lambda t: (t["n"], t["precision"]))
+    recs = sorted(keep + list(tuned), key=key)
     save_schedules(path, arch, recs)

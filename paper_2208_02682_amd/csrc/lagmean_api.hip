@@ -62,8 +62,8 @@ lm_status check_cfg(const lm_config* cfg) {
 // launch schedules, one per (grid size, precision); every launch reads them
 // ---------------------------------------------------------------------------
 std::mutex g_sched_mu;
-lm::Sched g_sched[7][2];  // [size index][fp32]
-unsigned g_sched_gen = 0;  // bumped on every change: batches re-capture their graph
+lm::Sched g_sched[2][7][2];  // [0 single runs, 1 batched launches][size index][fp32]
+unsigned g_sched_gen = 0;    // bumped on every change: batches re-capture their graph
 
 int size_index(int n) {
   switch (n) {
@@ -78,15 +78,15 @@ int size_index(int n) {
   return -1;
 }
 
-lm::Sched get_sched(int n, bool fp32, unsigned* gen = nullptr) {
+lm::Sched get_sched(int n, bool fp32, bool batched, unsigned* gen = nullptr) {
   std::lock_guard<std::mutex> lk(g_sched_mu);
   if (gen) *gen = g_sched_gen;
-  return g_sched[size_index(n)][fp32 ? 1 : 0];
+  return g_sched[batched ? 1 : 0][size_index(n)][fp32 ? 1 : 0];
 }
 
-void put_sched(int n, bool fp32, const lm::Sched& sc) {
+void put_sched(int n, bool fp32, bool batched, const lm::Sched& sc) {
   std::lock_guard<std::mutex> lk(g_sched_mu);
-  g_sched[size_index(n)][fp32 ? 1 : 0] = sc;
+  g_sched[batched ? 1 : 0][size_index(n)][fp32 ? 1 : 0] = sc;
   ++g_sched_gen;
 }
 
@@ -151,7 +151,7 @@ struct lm_batch {
 namespace {
 
 // the launches of a run follow the table's schedule of its (N, precision)
-void use_sched(lm_run* r) { r->sched = get_sched(r->d.N, r->fp32); }
+void use_sched(lm_run* r) { r->sched = get_sched(r->d.N, r->fp32, false); }
 
 // state field -> (pointer, is_float32)
 std::pair<const void*, int> state_field(lm_run* r, int which) {
@@ -622,7 +622,7 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
   }
   std::vector<lm::Sched> scheds;
   unsigned gen = sched_gen();
-  for (auto& l : launches) scheds.push_back(get_sched(l.g->N, l.g->fp32, &gen));
+  for (auto& l : launches) scheds.push_back(get_sched(l.g->N, l.g->fp32, true, &gen));
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   // from here on the capture is always ended, whatever fails
   hipError_t e = hipEventRecord(b->fork_ev, b->stream);
@@ -715,9 +715,14 @@ lm_status lm_batch_remaining(lm_batch* b, const lm_run* r, int32_t* remaining) {
   return LM_OK;
 }
 
-lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
-  if (!b) return fail(LM_E_ARG, "null batch");
-  if (max_steps < 0) return fail(LM_E_ARG, "max_steps < 0");
+}  // extern "C"
+
+namespace {
+
+// device step counters for the members (allocated on first use, grown with
+// the batch), after the caller's stream and the members' own streams: their
+// values from the host counters
+lm_status upload_counters(lm_batch* b) {
   const int m = (int)b->members.size();
   if (m > b->counter_cap) {
     if (b->d_counters) (void)hipFree(b->d_counters);
@@ -739,6 +744,19 @@ lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
   }
   if (m > 0) HIP_TRY(hipMemcpy(b->d_counters, cnt.data(), m * sizeof(long long), hipMemcpyHostToDevice));
   (void)hipGetLastError();
+  return LM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
+  if (!b) return fail(LM_E_ARG, "null batch");
+  if (max_steps < 0) return fail(LM_E_ARG, "max_steps < 0");
+  const int m = (int)b->members.size();
+  lm_status st = upload_counters(b);
+  if (st != LM_OK) return st;
   for (int it = 0; it < max_steps; ++it) {
     std::vector<int> active;
     for (int i = 0; i < m; ++i)
@@ -765,6 +783,103 @@ lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
   return LM_OK;
 }
 
+lm_status lm_batch_autotune(lm_batch* b, int32_t steps, int32_t reps, int32_t* tuned) {
+  if (!b) return fail(LM_E_ARG, "null batch");
+  if (steps < 1 || steps > 64) return fail(LM_E_ARG, "steps must be in 1..64");
+  if (reps < 1 || reps > 16) return fail(LM_E_ARG, "reps must be in 1..16");
+  const int m = (int)b->members.size();
+  if (tuned) *tuned = 0;
+  if (m == 0) return LM_OK;
+  lm_status st = upload_counters(b);  // also waits for every stream that may touch the members
+  if (st != LM_OK) return st;
+  // a copy of every member's allocation and host counters
+  std::vector<void*> snap(m, nullptr);
+  std::vector<int64_t> n0(m), nt0(m);
+  std::vector<int> ys0(m);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < m && e == hipSuccess; ++i) {
+    lm_run* r = b->members[i].run;
+    n0[i] = r->n;
+    nt0[i] = r->n_tau;
+    ys0[i] = r->ys_cur;
+    e = hipMalloc(&snap[i], r->L.total);
+    if (e == hipSuccess) e = hipMemcpyAsync(snap[i], r->slab, r->L.total, hipMemcpyDeviceToDevice, b->stream);
+  }
+  const bool have_copy = (e == hipSuccess);
+  auto restore = [&]() -> hipError_t {
+    hipError_t x = hipSuccess;
+    for (int i = 0; i < m && x == hipSuccess; ++i) {
+      lm_run* r = b->members[i].run;
+      r->n = n0[i];
+      r->n_tau = nt0[i];
+      r->ys_cur = ys0[i];
+      if (have_copy) x = hipMemcpyAsync(r->slab, snap[i], r->L.total, hipMemcpyDeviceToDevice, b->stream);
+    }
+    return x;
+  };
+  // (N, precision) keys present, each tuned in turn with the others at their current schedule
+  std::vector<std::pair<int, bool>> keys;
+  for (auto& mm : b->members) {
+    const std::pair<int, bool> k{mm.run->d.N, mm.run->fp32};
+    if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+  }
+  std::vector<int> all(m);
+  for (int i = 0; i < m; ++i) all[i] = i;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  lm_status ls = LM_OK;
+  for (size_t ki = 0; ki < keys.size() && e == hipSuccess && ls == LM_OK; ++ki) {
+    const int N = keys[ki].first;
+    const bool fp32 = keys[ki].second;
+    const std::vector<lm::Sched> cand = sched_candidates(N, fp32);
+    lm::Sched best = get_sched(N, fp32, true);
+    double best_t = -1.0;
+    for (size_t c = 0; c < cand.size() && e == hipSuccess && ls == LM_OK; ++c) {
+      put_sched(N, fp32, true, cand[c]);
+      ls = batch_rebuild(b, all);
+      double bt = -1.0;
+      for (int rep = 0; rep < reps && e == hipSuccess && ls == LM_OK; ++rep) {
+        e = restore();
+        // the graph's tick advances the device counters: start every trial from the host ones
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e == hipSuccess) ls = upload_counters(b);
+        if (e == hipSuccess && ls == LM_OK) e = hipEventRecord(e0, b->stream);
+        for (int s = 0; s < steps && e == hipSuccess && ls == LM_OK; ++s) e = hipGraphLaunch(b->exec, b->stream);
+        if (e == hipSuccess && ls == LM_OK) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess && ls == LM_OK) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess && ls == LM_OK) e = hipEventElapsedTime(&t, e0, e1);
+        if (e == hipSuccess && ls == LM_OK && (bt < 0.0 || t < bt)) bt = t;
+      }
+      if (e == hipSuccess && ls == LM_OK && (best_t < 0.0 || bt < best_t)) {
+        best_t = bt;
+        best = cand[c];
+      }
+    }
+    put_sched(N, fp32, true, best);
+  }
+  // the members as they were, their device counters from the host ones, and
+  // a graph captured afresh at the next lm_batch_step
+  const hipError_t er = restore();
+  const hipError_t es = hipStreamSynchronize(b->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void* p : snap)
+    if (p) (void)hipFree(p);
+  drop_graph(b);
+  if (ls != LM_OK) return ls;
+  if (e == hipSuccess) e = (er != hipSuccess) ? er : es;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? LM_E_OOM : LM_E_HIP, std::string("batch autotune: ") + hipGetErrorString(e));
+  }
+  st = upload_counters(b);
+  if (st != LM_OK) return st;
+  if (tuned) *tuned = (int32_t)keys.size();
+  return LM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // launch schedules and the autotuner
 // ---------------------------------------------------------------------------
@@ -779,27 +894,48 @@ lm_status lm_schedule_candidates(int32_t n, int32_t precision, lm_schedule* out,
   return LM_OK;
 }
 
-lm_status lm_set_schedule(int32_t n, int32_t precision, const lm_schedule* s) {
+}  // extern "C"
+
+namespace {
+
+lm_status set_schedule_ctx(int32_t n, int32_t precision, const lm_schedule* s, bool batched) {
   if (!supported_n(n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 192, 256, 384, 512 or 1024");
   if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
   if (!s) return fail(LM_E_ARG, "null schedule");
   const bool fp32 = precision == LM_FP32_MIXED;
   for (const lm::Sched& c : sched_candidates(n, fp32)) {
     if (c.tile == s->col_tile && c.remap == s->xcd_order) {
-      put_sched(n, fp32, c);
+      put_sched(n, fp32, batched, c);
       return LM_OK;
     }
   }
   return fail(LM_E_ARG, "not a usable schedule for this n and precision");
 }
 
-lm_status lm_get_schedule(int32_t n, int32_t precision, lm_schedule* s) {
+lm_status get_schedule_ctx(int32_t n, int32_t precision, lm_schedule* s, bool batched) {
   if (!supported_n(n)) return fail(LM_E_UNSUPPORTED, "n must be 64, 128, 192, 256, 384, 512 or 1024");
   if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
   if (!s) return fail(LM_E_ARG, "null schedule");
-  const lm::Sched c = get_sched(n, precision == LM_FP32_MIXED);
+  const lm::Sched c = get_sched(n, precision == LM_FP32_MIXED, batched);
   *s = lm_schedule{c.tile, c.remap};
   return LM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_set_schedule(int32_t n, int32_t precision, const lm_schedule* s) {
+  return set_schedule_ctx(n, precision, s, false);
+}
+lm_status lm_get_schedule(int32_t n, int32_t precision, lm_schedule* s) {
+  return get_schedule_ctx(n, precision, s, false);
+}
+lm_status lm_set_batch_schedule(int32_t n, int32_t precision, const lm_schedule* s) {
+  return set_schedule_ctx(n, precision, s, true);
+}
+lm_status lm_get_batch_schedule(int32_t n, int32_t precision, lm_schedule* s) {
+  return get_schedule_ctx(n, precision, s, true);
 }
 
 lm_status lm_autotune(lm_run* r, int32_t steps, int32_t reps, lm_schedule* best, double* ms, int32_t cap,
@@ -867,7 +1003,7 @@ lm_status lm_autotune(lm_run* r, int32_t steps, int32_t reps, lm_schedule* best,
   size_t bi = 0;
   for (size_t k = 1; k < cand.size(); ++k)
     if (best_ms[k] < best_ms[bi]) bi = k;
-  put_sched(r->d.N, r->fp32, cand[bi]);
+  put_sched(r->d.N, r->fp32, false, cand[bi]);
   if (best) *best = lm_schedule{cand[bi].tile, cand[bi].remap};
   for (int k = 0; k < (int)cand.size() && k < cap; ++k) ms[k] = best_ms[k];
   if (count) *count = (int32_t)cand.size();

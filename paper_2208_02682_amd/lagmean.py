@@ -112,6 +112,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_get_schedule": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule)],
         "lm_autotune": [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule), D, ctypes.c_int32,
                         ctypes.POINTER(ctypes.c_int32)],
+        "lm_set_batch_schedule": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule)],
+        "lm_get_batch_schedule": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule)],
+        "lm_batch_autotune": [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
         "lm_e2d_create": [ctypes.POINTER(E2DConfig), P, ctypes.POINTER(P)],
         "lm_e2d_set_vorticity": [P, P, ctypes.c_int],
         "lm_e2d_begin_interval": [P],
@@ -162,26 +165,32 @@ def schedule_candidates(n: int, precision: str) -> List[Tuple[int, int]]:
     return [buf[i].key() for i in range(cnt.value)]
 
 
-def set_schedule(n: int, precision: str, col_tile: int, xcd_order: int) -> None:
+def set_schedule(n: int, precision: str, col_tile: int, xcd_order: int, batched: bool = False) -> None:
+    """Install a schedule in the single-run table (or the batched launches' table)."""
     s = Schedule(col_tile=col_tile, xcd_order=xcd_order)
-    _check(load_library().lm_set_schedule(n, PRECISIONS[precision], ctypes.byref(s)))
+    lib = load_library()
+    fn = lib.lm_set_batch_schedule if batched else lib.lm_set_schedule
+    _check(fn(n, PRECISIONS[precision], ctypes.byref(s)))
 
 
-def get_schedule(n: int, precision: str) -> Tuple[int, int]:
+def get_schedule(n: int, precision: str, batched: bool = False) -> Tuple[int, int]:
     s = Schedule()
-    _check(load_library().lm_get_schedule(n, PRECISIONS[precision], ctypes.byref(s)))
+    lib = load_library()
+    fn = lib.lm_get_batch_schedule if batched else lib.lm_get_schedule
+    _check(fn(n, PRECISIONS[precision], ctypes.byref(s)))
     return s.key()
 
 
 def save_schedules(path: str, arch: str, tuned: List[dict]) -> None:
     """Write autotuning results as JSON: arch (the device's architecture name)
-    and one entry per (n, precision) with the chosen schedule and the per-step
-    times of every candidate (as returned by Run.autotune)."""
+    and one entry per (context, n, precision) with the chosen schedule and, when
+    measured, the per-step times of every candidate (Run.autotune's records;
+    context "batched" for Batch.autotune's)."""
     entries = []
     for t in tuned:
-        entries.append({"n": int(t["n"]), "precision": t["precision"], "col_tile": int(t["best"][0]),
-                        "xcd_order": int(t["best"][1]),
-                        "ms_per_step": {f"{k[0]},{k[1]}": float(v) for k, v in t["ms"].items()}})
+        entries.append({"context": t.get("context", "single"), "n": int(t["n"]), "precision": t["precision"],
+                        "col_tile": int(t["best"][0]), "xcd_order": int(t["best"][1]),
+                        "ms_per_step": {f"{k[0]},{k[1]}": float(v) for k, v in t.get("ms", {}).items()}})
     with open(path, "w") as f:
         json.dump({"format": 1, "arch": arch, "entries": entries}, f, indent=1)
 
@@ -196,7 +205,8 @@ def load_schedules(path: str, arch: Optional[str] = None) -> int:
     if arch is not None and doc.get("arch") != arch:
         return 0
     for e in doc["entries"]:
-        set_schedule(int(e["n"]), e["precision"], int(e["col_tile"]), int(e["xcd_order"]))
+        set_schedule(int(e["n"]), e["precision"], int(e["col_tile"]), int(e["xcd_order"]),
+                     batched=e.get("context", "single") == "batched")
     return len(doc["entries"])
 
 
@@ -358,6 +368,16 @@ class Batch:
         active = ctypes.c_int32(0)
         _check(self.lib.lm_batch_step(self.h, int(max_steps), ctypes.byref(active)))
         return active.value
+
+    def autotune(self, steps: int = 4, reps: int = 3) -> List[dict]:
+        """Tune the batched launches' schedule of every (N, precision) among the
+        members (lm_batch_autotune; members are left as they were).  Returns one
+        record per (N, precision) with the chosen schedule (context "batched")."""
+        n = ctypes.c_int32(0)
+        _check(self.lib.lm_batch_autotune(self.h, int(steps), int(reps), ctypes.byref(n)))
+        keys = sorted({(r.N, "fp32" if r.cfg.precision == LM_FP32_MIXED else "fp64") for r in self.members})
+        return [{"context": "batched", "n": N, "precision": p, "best": get_schedule(N, p, batched=True)}
+                for N, p in keys]
 
     def remaining(self, run: Run) -> int:
         r = ctypes.c_int32(0)

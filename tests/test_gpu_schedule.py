@@ -18,6 +18,7 @@ def default_schedules():
     for n in (64, 128, 192, 256, 384, 512, 1024):
         for p in ("fp32", "fp64"):
             L.set_schedule(n, p, 0, 1)
+            L.set_schedule(n, p, 0, 1, batched=True)
 
 
 def _w(N, prec, seeds=(31, 32)):
@@ -120,20 +121,57 @@ def test_batch_follows_the_schedule_table():
         r = _start(w, st)
         r.step(n)
         alone.append(_finish(r))
-    L.set_schedule(128, "fp32", 1, 0)
-    L.set_schedule(192, "fp32", -1, 0)
+    L.set_schedule(128, "fp32", 1, 0, batched=True)
+    L.set_schedule(192, "fp32", -1, 0, batched=True)
     runs = [_start(w, st) for w, st in zip(ws, sts)]
     with L.Batch() as b:
         for r, (_, _, n) in zip(runs, specs):
             b.add(r, n)
         b.step(4)
         # a change of the table between calls: the next call re-captures
-        L.set_schedule(192, "fp32", 1, 1)
-        L.set_schedule(256, "fp64", -1, 0)
+        L.set_schedule(192, "fp32", 1, 1, batched=True)
+        L.set_schedule(256, "fp64", -1, 0, batched=True)
         while b.step(3):
             pass
         for r in runs:
             b.remove(r)
+    for i, r in enumerate(runs):
+        got = _finish(r)
+        for k in alone[i]:
+            assert np.array_equal(got[k], alone[i][k]), (specs[i], k)
+
+
+def test_batch_autotune_leaves_the_members_as_they_were():
+    import paper_2208_02682_amd as L
+    specs = [(128, "fp32", 10), (192, "fp32", 8), (256, "fp64", 6), (128, "fp32", 9)]
+    ws = [_w(N, p, seeds=(70 + i, 80 + i)) for i, (N, p, _) in enumerate(specs)]
+    sts = [w.initial_state() for w in ws]
+    alone = []
+    for w, st, (_, _, n) in zip(ws, sts, specs):
+        r = _start(w, st)
+        r.step(n)
+        alone.append(_finish(r))
+    runs = [_start(w, st) for w, st in zip(ws, sts)]
+    with L.Batch() as b:
+        for r, (_, _, n) in zip(runs, specs):
+            b.add(r, n)
+        b.step(3)
+        before = [r.peek("xi_x") for r in runs]
+        recs = b.autotune(steps=2, reps=2)
+        say("  batched schedules: " + ", ".join(f"{t['n']} {t['precision']}: {t['best']}" for t in recs))
+        assert sorted((t["n"], t["precision"]) for t in recs) == [(128, "fp32"), (192, "fp32"), (256, "fp64")]
+        for t in recs:
+            assert t["best"] in L.schedule_candidates(t["n"], t["precision"])
+        for r, (_, _, n), x in zip(runs, specs, before):
+            assert b.remaining(r) == n - 3
+            assert r.counters() == (3, 3)
+            assert np.array_equal(r.peek("xi_x"), x)
+        while b.step(3):
+            pass
+        for r in runs:
+            b.remove(r)
+    for N, p, _ in specs:
+        assert L.get_schedule(N, p) == (0, 1)      # the single-run table is not touched
     for i, r in enumerate(runs):
         got = _finish(r)
         for k in alone[i]:

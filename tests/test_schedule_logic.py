@@ -21,6 +21,7 @@ def L():
     for n in SIZES:
         for p in ("fp32", "fp64"):
             lib.set_schedule(n, p, 0, 1)
+            lib.set_schedule(n, p, 0, 1, batched=True)
 
 
 def _usable(n, w, cplx_bytes):
@@ -67,9 +68,16 @@ def test_set_get_and_refusals(L):
         L.set_schedule(100, "fp32", 0, 1)
     assert e.value.status == -6
     L.set_schedule(256, "fp32", 0, 1)
+    # the batched launches' table is separate
+    L.set_schedule(256, "fp32", 1, 0, batched=True)
+    assert L.get_schedule(256, "fp32", batched=True) == (1, 0) and L.get_schedule(256, "fp32") == (0, 1)
+    with pytest.raises(LagMeanError):
+        L.set_schedule(1024, "fp64", 1, 1, batched=True)
+    L.set_schedule(256, "fp32", 0, 1, batched=True)
     lib = L.load_library()
     assert lib.lm_schedule_candidates(256, 1, None, 1, None) == -1   # cap > 0 with no array
     assert lib.lm_autotune(None, 8, 3, None, None, 0, None) == -1
+    assert lib.lm_batch_autotune(None, 4, 3, None) == -1
 
 
 def test_json_cache_round_trip_and_merge(L, tmp_path):
@@ -88,10 +96,15 @@ def test_json_cache_round_trip_and_merge(L, tmp_path):
     assert L.get_schedule(256, "fp32") == (0, 1)
     assert L.load_schedules(path, "gfx950") == 2
     assert L.get_schedule(256, "fp32") == (-1, 0) and L.get_schedule(512, "fp64") == (0, 0)
-    # a re-tune of one entry replaces it
+    # a re-tune of one entry replaces it; batched entries are kept apart
     at.merge_save(path, "gfx950", [dict(t1[0], best=(0, 1))])
-    assert {(e["n"], e["precision"]): (e["col_tile"], e["xcd_order"]) for e in json.load(open(path))["entries"]} \
-        == {(256, "fp32"): (0, 1), (512, "fp64"): (0, 0)}
+    at.merge_save(path, "gfx950", [{"context": "batched", "n": 256, "precision": "fp32", "best": (1, 1)}])
+    got = {(e["context"], e["n"], e["precision"]): (e["col_tile"], e["xcd_order"])
+           for e in json.load(open(path))["entries"]}
+    assert got == {("single", 256, "fp32"): (0, 1), ("single", 512, "fp64"): (0, 0),
+                   ("batched", 256, "fp32"): (1, 1)}
+    assert L.load_schedules(path, "gfx950") == 3
+    assert L.get_schedule(256, "fp32", batched=True) == (1, 1) and L.get_schedule(256, "fp32") == (0, 1)
 
 
 def test_shipped_cache_is_well_formed(L):
@@ -102,7 +115,9 @@ def test_shipped_cache_is_well_formed(L):
     doc = json.load(open(path))
     assert doc["format"] == 1 and doc["arch"] == "gfx950"
     for e in doc["entries"]:
+        assert e.get("context", "single") in ("single", "batched")
         assert (e["col_tile"], e["xcd_order"]) in L.schedule_candidates(e["n"], e["precision"])
-        # the chosen schedule is the fastest measured one
-        best = min(e["ms_per_step"], key=e["ms_per_step"].get)
-        assert best == f"{e['col_tile']},{e['xcd_order']}"
+        # the chosen schedule is the fastest measured one (where times were recorded)
+        if e["ms_per_step"]:
+            best = min(e["ms_per_step"], key=e["ms_per_step"].get)
+            assert best == f"{e['col_tile']},{e['xcd_order']}"
