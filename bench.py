@@ -501,6 +501,13 @@ def main(argv=None) -> int:
               f"--gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
 
+    if a.mode == "serve":
+        # the last run of this mode (schedule cache applied, 577 requests) ended in a
+        # segmentation fault of the host process after about 200 requests; until its
+        # cause is found the mode stays disabled (the serving loop's tests still run)
+        print("bench.py --mode serve is disabled: its last run ended in a host segmentation fault "
+              "whose cause has not been found", file=sys.stderr)
+        return 2
     if a.mode in ("batch", "serve", "euler", "tune"):
         rec = {"batch": bench_batch, "serve": bench_serve, "euler": bench_euler, "tune": bench_tune}[a.mode](a)
         print(json.dumps(rec), flush=True)
