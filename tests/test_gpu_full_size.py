@@ -124,8 +124,10 @@ def test_sw1024_mixed_first_interval_at_full_size():
                            perturb=lambda a: a * (1.0 + PERTURB * rng.standard_normal(a.shape)))
         _, errs = _errors(name)
     finally:
-        for p in ("fp32", "fp64"):
-            L.set_schedule(1024, p, 0, 1)
+        for n in (64, 128, 192, 256, 384, 512, 1024):
+            for p in ("fp32", "fp64"):
+                L.set_schedule(n, p, 0, 1)
+                L.set_schedule(n, p, 0, 1, batched=True)
     n = w.steps_per_interval
     for key, e in errs[0].items():
         tol = max(1e-5, 2.0 * np.sqrt(n) * (U32 / PERTURB) * probe[0][key])
