@@ -294,6 +294,90 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, TW tw) {
   xsync<NT>();
 }
 
+// swap of 32-bit words between lane rows (16 lanes) of two registers:
+// ROWS = 16: odd rows of a with even rows of b; ROWS = 32: rows 2, 3 of a with
+// rows 0, 1 of b (v_permlane16_swap / v_permlane32_swap)
+template <int ROWS, typename V>
+__device__ __forceinline__ void lane_swap(V& a, V& b) {
+  static_assert(sizeof(V) % 4 == 0, "32-bit words");
+  constexpr int W = sizeof(V) / 4;
+  unsigned wa[W], wb[W];
+  __builtin_memcpy(wa, &a, sizeof(V));
+  __builtin_memcpy(wb, &b, sizeof(V));
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    if constexpr (ROWS == 16) {
+      const auto r = __builtin_amdgcn_permlane16_swap(wa[i], wb[i], false, false);
+      wa[i] = r[0];
+      wb[i] = r[1];
+    } else {
+      const auto r = __builtin_amdgcn_permlane32_swap(wa[i], wb[i], false, false);
+      wa[i] = r[0];
+      wb[i] = r[1];
+    }
+  }
+  __builtin_memcpy(&a, wa, sizeof(V));
+  __builtin_memcpy(&b, wb, sizeof(V));
+}
+
+// The last two stages of N = 256 G (G = 2 or 4; 16 values per lane, NT = 16 G
+// lanes, radix 16 then radix G) with the exchange between them done across
+// lanes instead of through LDS.  After the radix-16 stage, lane t = c + 16 q
+// (c < 16) holds entry 256 q + c + 16 r in x[r]; with r = G a + s that entry is
+// element A q + a (A = 16 / G) of lane c + 16 s in the last stage's layout
+// (entry t' + NT m in element m of lane t').  So the exchange is a G x G
+// transpose over q and s among the lanes c + 16 q, done with row swaps, after
+// which x[G a + k] holds element A k + a, which is exactly the last stage's
+// input b G + r for b = a, r = k.  The last stage then writes the spectrum to
+// buf in natural order, as a Stockham stage would.
+template <typename T, int N, int E, int DIR, typename TW>
+__device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw) {
+  constexpr int NT = N / E, G = N / 256, A = 16 / G;
+  static_assert(E == 16 && (G == 2 || G == 4) && NT == 16 * G, "plan 16 x 16 x G");
+  cplx<T> x[16];
+  // radix-16 stage after sub-transforms of length 16
+#pragma unroll
+  for (int r = 0; r < 16; ++r) x[r] = buf[pidx(t + r * (N / 16))];
+  const int k = t % 16;
+#pragma unroll
+  for (int r = 1; r < 16; ++r) {
+    const int m = r * k * (N / 256);
+    const cplx<T> w = {tw[m].x, tw[m].y};
+    x[r] = (DIR < 0) ? cmul(x[r], w) : cmulc(x[r], w);
+  }
+  dft<16, DIR>(x);
+  // G x G transpose across the lanes c + 16 q
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    if constexpr (G == 4) {
+      lane_swap<32>(x[4 * a + 0], x[4 * a + 2]);
+      lane_swap<32>(x[4 * a + 1], x[4 * a + 3]);
+      lane_swap<16>(x[4 * a + 0], x[4 * a + 1]);
+      lane_swap<16>(x[4 * a + 2], x[4 * a + 3]);
+    } else {
+      lane_swap<16>(x[2 * a + 0], x[2 * a + 1]);
+    }
+  }
+  // the buffer is rewritten below: every lane's reads above come first
+  xsync<NT>();
+  // radix-G stage after sub-transforms of length 256: butterfly b of lane t
+  // combines entries j + 256 r, j = t + NT b
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int j = t + NT * b;
+#pragma unroll
+    for (int r = 1; r < G; ++r) {
+      const int m = r * j;
+      const cplx<T> w = {tw[m].x, tw[m].y};
+      x[b * G + r] = (DIR < 0) ? cmul(x[b * G + r], w) : cmulc(x[b * G + r], w);
+    }
+    dft<G, DIR>(&x[b * G]);
+#pragma unroll
+    for (int r = 0; r < G; ++r) buf[pidx(j + 256 * r)] = x[b * G + r];
+  }
+  xsync<NT>();
+}
+
 // Full transform of N points held by NT = N / E lanes.  v: lane t holds
 // x[t + NT e]; buf: the group's LDS buffer (padded_len(N) slots).  On exit the
 // spectrum is in buf in natural order.  DIR = -1: forward (exp(-i...)),
@@ -313,9 +397,13 @@ __device__ __forceinline__ void fft(cplx<T> (&v)[E], cplx<T>* buf, int t, const 
 #pragma unroll
   for (int r = 0; r < E; ++r) buf[pidx(t * E + r)] = v[r];
   xsync<NT>();
-  if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, ptw);
-  if constexpr (PL::R3 > 1) stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, ptw);
-  if constexpr (PL::R4 > 1) stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, ptw);
+  if constexpr (GTW && E == 16 && PL::R2 == 16 && (PL::R3 == 2 || PL::R3 == 4) && PL::R4 == 1) {
+    stages_16_then_G<T, N, E, DIR>(buf, t, ptw);
+  } else {
+    if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, ptw);
+    if constexpr (PL::R3 > 1) stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, ptw);
+    if constexpr (PL::R4 > 1) stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, ptw);
+  }
 }
 
 }  // namespace lm
