@@ -75,6 +75,7 @@ def main(argv=None):
     i0 = k0 = 0
     if a.checkpoint and os.path.exists(a.checkpoint):
         i0, k0 = load_checkpoint(a.checkpoint, r, store)
+        store["n_intervals"] = n_int  # this invocation's count, whatever the checkpoint's was
         print(f"resumed at interval {i0} step {k0}", flush=True)
     t0 = time.time()
     for i in range(i0, n_int):
