@@ -330,8 +330,8 @@ __device__ __forceinline__ void lane_swap(V& a, V& b) {
 // which x[G a + k] holds element A k + a, which is exactly the last stage's
 // input b G + r for b = a, r = k.  The last stage then writes the spectrum to
 // buf in natural order, as a Stockham stage would.
-template <typename T, int N, int E, int DIR, typename TW>
-__device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw) {
+template <typename T, int N, int E, int DIR, bool KEEP, typename TW>
+__device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw, cplx<T> (&out)[E]) {
   constexpr int NT = N / E, G = N / 256, A = 16 / G;
   static_assert(E == 16 && (G == 2 || G == 4) && NT == 16 * G, "plan 16 x 16 x G");
   cplx<T> x[16];
@@ -372,10 +372,22 @@ __device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw) {
       x[b * G + r] = (DIR < 0) ? cmul(x[b * G + r], w) : cmulc(x[b * G + r], w);
     }
     dft<G, DIR>(&x[b * G]);
+    // entry j + 256 r = t + NT (b + A r)
 #pragma unroll
-    for (int r = 0; r < G; ++r) buf[pidx(j + 256 * r)] = x[b * G + r];
+    for (int r = 0; r < G; ++r) {
+      if constexpr (KEEP) out[b + A * r] = x[b * G + r];
+      else buf[pidx(j + 256 * r)] = x[b * G + r];
+    }
   }
   xsync<NT>();
+}
+
+// whether fft<..., GTW> takes the lane-swap path, which can leave its output in
+// the lanes' registers (KEEP) instead of the buffer
+template <int N, int E, bool GTW>
+__host__ __device__ constexpr bool fft_keeps() {
+  return GTW && E == 16 && Plan<N, E>::R2 == 16 && (Plan<N, E>::R3 == 2 || Plan<N, E>::R3 == 4) &&
+         Plan<N, E>::R4 == 1;
 }
 
 // Full transform of N points held by NT = N / E lanes.  v: lane t holds
@@ -384,7 +396,7 @@ __device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw) {
 // DIR = +1: inverse (unnormalised).  GTW: read the twiddles with global loads
 // (else generic ones, which also count against the LDS counter: measured
 // faster in the dynamics row pass, slower in the others).
-template <typename T, int N, int E, int DIR, bool GTW = true>
+template <typename T, int N, int E, int DIR, bool GTW = true, bool KEEP = false>
 __device__ __forceinline__ void fft(cplx<T> (&v)[E], cplx<T>* buf, int t, const cplx<T>* __restrict__ tw) {
   using PL = Plan<N, E>;
   constexpr int NT = N / E;
@@ -397,9 +409,10 @@ __device__ __forceinline__ void fft(cplx<T> (&v)[E], cplx<T>* buf, int t, const 
 #pragma unroll
   for (int r = 0; r < E; ++r) buf[pidx(t * E + r)] = v[r];
   xsync<NT>();
-  if constexpr (GTW && E == 16 && PL::R2 == 16 && (PL::R3 == 2 || PL::R3 == 4) && PL::R4 == 1) {
-    stages_16_then_G<T, N, E, DIR>(buf, t, ptw);
+  if constexpr (fft_keeps<N, E, GTW>()) {
+    stages_16_then_G<T, N, E, DIR, KEEP>(buf, t, ptw, v);
   } else {
+    static_assert(!KEEP, "only the lane-swap plans keep their output in registers");
     if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, ptw);
     if constexpr (PL::R3 > 1) stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, ptw);
     if constexpr (PL::R4 > 1) stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, ptw);

@@ -96,10 +96,14 @@ template <typename T, int N, bool GTW = true>
 __device__ __forceinline__ void inverse_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* buf, int t,
                                             const cplx<T>* __restrict__ tw) {
   constexpr int E = fft_E<N>(), NT = N / E;
-  fft<T, N, E, +1, GTW>(z, buf, t, tw);
+  if constexpr (fft_keeps<N, E, GTW>()) {
+    fft<T, N, E, +1, GTW, true>(z, buf, t, tw);
+  } else {
+    fft<T, N, E, +1, GTW>(z, buf, t, tw);
 #pragma unroll
-  for (int e = 0; e < E; ++e) z[e] = buf[pidx(t + NT * e)];
-  xsync<NT>();
+    for (int e = 0; e < E; ++e) z[e] = buf[pidx(t + NT * e)];
+    xsync<NT>();
+  }
   sched_fence();
 }
 

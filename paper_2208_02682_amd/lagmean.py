@@ -83,6 +83,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2208_02682_amd.build`")
+    # One HIP runtime per process.  PyTorch ships its own libamdhip64 (same
+    # soname); loaded first, it is the runtime the library binds to.  Loaded
+    # after the library, torch would bring a second runtime that does not see
+    # the GPU.  So torch, when present, is loaded before the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     D = ctypes.POINTER(ctypes.c_double)
