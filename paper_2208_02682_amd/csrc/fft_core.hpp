@@ -392,10 +392,11 @@ __host__ __device__ constexpr bool fft_keeps() {
 
 // Full transform of N points held by NT = N / E lanes.  v: lane t holds
 // x[t + NT e]; buf: the group's LDS buffer (padded_len(N) slots).  On exit the
-// spectrum is in buf in natural order.  DIR = -1: forward (exp(-i...)),
+// spectrum is in buf in natural order, or, with KEEP (lane-swap plans only), in
+// v with lane t holding entry t + NT e.  DIR = -1: forward (exp(-i...)),
 // DIR = +1: inverse (unnormalised).  GTW: read the twiddles with global loads
 // (else generic ones, which also count against the LDS counter: measured
-// faster in the dynamics row pass, slower in the others).
+// faster in the dynamics row pass's forward transforms, slower elsewhere).
 template <typename T, int N, int E, int DIR, bool GTW = true, bool KEEP = false>
 __device__ __forceinline__ void fft(cplx<T> (&v)[E], cplx<T>* buf, int t, const cplx<T>* __restrict__ tw) {
   using PL = Plan<N, E>;

@@ -276,7 +276,7 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
 
   cplx<T> uv[E], hz[E];
   load_pair<T, N, false, false>(uv, ICr + IC_U * rf, ICr + IC_V * rf, t);
-  inverse_row<T, N, false>(uv, buf, t, P.tw);
+  inverse_row<T, N>(uv, buf, t, P.tw);
   // (eta + i zeta): zeta spectrum = i kx C_v - C_uy
   {
     const cplx<T>* Ch = ICr + IC_H * rf;
@@ -297,7 +297,7 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
       hz[r] = (lo || hi) ? cplx<T>{a.x - b.y, a.y + b.x} : cplx<T>{T(0), T(0)};
     }
   }
-  inverse_row<T, N, false>(hz, buf, t, P.tw);
+  inverse_row<T, N>(hz, buf, t, P.tw);
 
   P4<T>* out = P.uvhz + (size_t)y * N;
 #pragma unroll
