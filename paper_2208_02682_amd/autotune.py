@@ -58,7 +58,7 @@ def tune(specs: Iterable[Tuple[int, str]], config_for: Callable[[int, str], Conf
     return out
 
 
-def tune_batch(runs: List[Run], *, warm_steps: int = 20, steps: int = 4, reps: int = 3) -> List[dict]:
+def tune_batch(runs: List[Run], *, warm_steps: int = 20, steps: int = 8, reps: int = 5) -> List[dict]:
     """Autotune the batched launches' schedules on runs (each with a state; an
     interval is opened here and warm_steps steps taken first): they join one
     batch, lm_batch_autotune tunes every (N, precision) among them, and the
