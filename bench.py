@@ -27,7 +27,9 @@ Three more modes print one JSON line each:
                  T = 25) with strategy 1 pseudospectral and semi-Lagrangian, and
                  the semi-Lagrangian kernel at 1024^2 against HBM;
   --mode tune  : the autotuner over every grid size and precision, written to the
-                 schedule cache (paper_2208_02682_amd/schedules_<arch>.json).
+                 schedule cache (paper_2208_02682_amd/schedules_<arch>.json);
+  --mode latency : p50/p99 solve latency of the serving mix's requests served one
+                 at a time (state handed over -> all means on the host).
 Every mode applies the shipped schedule cache first (--no-schedule-cache: the
 default schedules); --autotune measures the mode's own sizes first.
 """
@@ -410,6 +412,68 @@ def bench_serve(a) -> dict:
     return rec
 
 
+def bench_latency(a) -> dict:
+    """Solve latency of averaging requests served one at a time (no batching,
+    no queueing): for each request of the serving workload's mix, the time
+    from handing over its initial state to having every mean on the host.
+    Runs are pooled per configuration, as in serving; states are generated
+    before any clock starts."""
+    import numpy as np
+    import torch
+    from paper_2208_02682_amd import Run
+    from synth.workloads import serving_requests
+
+    reqs = serving_requests(rate=20.0, duration=a.latency_window, seed=7)
+    states = generate_states([r.run for r in reqs])
+    torch.cuda.set_device(0)
+    sizes = sorted({r.run.N for r in reqs})
+    first = {}
+    for r, st in zip(reqs, states):
+        first.setdefault(r.run.N, (r.run, st))
+    source = apply_schedules(a, [(N, "fp32") for N in sizes], lambda N, p: _cfg(first[N][0], p),
+                             lambda N: first[N][1])
+    pool = {}
+    for N in sizes:  # one run per grid size, created and warmed up before the clock starts
+        w, st = first[N]
+        run = Run(_cfg(w))
+        run.set_state(*st)
+        run.begin_interval()
+        run.step(2)
+        run.end_interval()
+        pool[N] = run
+    lat, work = [], 0
+    t_all = time.perf_counter()
+    for r, st in zip(reqs, states):
+        run = pool[r.run.N]
+        t0 = time.perf_counter()
+        run.set_state(*st)
+        run.begin_interval()
+        run.step(r.run.steps_per_interval)
+        run.end_interval()
+        out = run.outputs()
+        lat.append(time.perf_counter() - t0)
+        work += r.run.N * r.run.N * r.run.steps_per_interval
+        assert all(np.isfinite(v).all() for v in out.values())
+    elapsed = time.perf_counter() - t_all
+    for run in pool.values():
+        run.close()
+    lat = np.array(lat)
+    by_n = {}
+    for N in sizes:
+        x = np.array([l for l, r in zip(lat, reqs) if r.run.N == N])
+        by_n[str(N)] = {"requests": int(len(x)), "p50_s": float(np.percentile(x, 50)),
+                        "p99_s": float(np.percentile(x, 99))}
+    return {"metric": "p50/p99 solve latency, requests served one at a time", "value": float(np.percentile(lat, 99)),
+            "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"averaging requests, N in {sizes} with probabilities 0.4/0.3/0.2/0.1, the "
+                                   f"64^2 recipe scaled to N, float32 transforms with float64 xi and P, "
+                                   f"T ~ U[1, 8] wave periods, dt = 0.64/N, seed 7, first {len(reqs)} requests",
+                       "schedule_source": source},
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "requests": len(reqs), "by_N": by_n,
+            "throughput_pt_steps_per_s": work / elapsed}
+
+
 def bench_euler(a) -> dict:
     """The two-dimensional incompressible test of section 4.1 (128^2, dt 0.005,
     T = 25) with strategy 1 pseudospectral and semi-Lagrangian, plus the
@@ -475,7 +539,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the event-timed replay (roofline fields become null)")
-    ap.add_argument("--mode", choices=("step", "batch", "serve", "euler", "tune"), default="step")
+    ap.add_argument("--mode", choices=("step", "batch", "serve", "euler", "tune", "latency"), default="step")
+    ap.add_argument("--latency-window", type=float, default=3.0,
+                    help="latency: requests of this many seconds of the 20 /s arrival sequence")
     ap.add_argument("--autotune", action="store_true",
                     help="measure the launch schedules of the mode's grid sizes first (lm_autotune)")
     ap.add_argument("--no-schedule-cache", action="store_true",
@@ -508,8 +574,9 @@ def main(argv=None) -> int:
         print("bench.py --mode serve is disabled: its last run ended in a host segmentation fault "
               "whose cause has not been found", file=sys.stderr)
         return 2
-    if a.mode in ("batch", "serve", "euler", "tune"):
-        rec = {"batch": bench_batch, "serve": bench_serve, "euler": bench_euler, "tune": bench_tune}[a.mode](a)
+    if a.mode in ("batch", "serve", "euler", "tune", "latency"):
+        rec = {"batch": bench_batch, "serve": bench_serve, "euler": bench_euler, "tune": bench_tune,
+               "latency": bench_latency}[a.mode](a)
         print(json.dumps(rec), flush=True)
         return 0
     import numpy as np
