@@ -76,3 +76,17 @@ def test_product_path_does_not_import_the_oracle():
     code = ("import sys; import paper_2208_02682_amd, paper_2208_02682_amd.lagmean, paper_2208_02682_amd.build;"
             "assert not any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules), 'oracle imported'")
     subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)
+
+
+def test_header_is_plain_c(tmp_path):
+    # the boundary is a C ABI: the header compiles as C99 with warnings as errors
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "h.c"
+    src.write_text('#include "lagmean.h"\nint main(void) { lm_schedule s = {0, 1}; lm_config c; (void)s; (void)c;'
+                   ' return (int)LM_OK; }\n')
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", INCLUDE, "-c", str(src), "-o",
+                    str(tmp_path / "h.o")], check=True)
