@@ -652,7 +652,7 @@ def main(argv=None) -> int:
     pts = w.N * w.N
     value = pts * a.steps / (ms * 1e-3)
     rec = {
-        "metric": "grid-pt RK4 steps/s incl. mean PDEs @1024^2",
+        "metric": f"grid-pt RK4 steps/s incl. mean PDEs @{w.N}^2",
         "value": value,
         "unit": "grid-pt RK4 steps/s",
         "n_gpus": 1,
