@@ -97,8 +97,10 @@ def algorithmic_bytes(N: int, fp32: bool):
     rows_rhs = 16 * rowfield + phys4 + 8 * rowfield
     # columns: 13 row spectra in, 20 column-pass outputs out, state Y read,
     # accumulator read (stages 2-4) and written (stages 1-3), Y written (stage 4),
-    # stage values of u, v, h read and written
-    columns = 13 * rowfield + 20 * rowfield + (1.0 + 0.75 + 0.75 + 0.25) * state + 6 * sp * cT
+    # stage values of u, v, h read and written; float32 state also reads and
+    # writes its trailing words in stage 4 (compensated RK4 update)
+    comp = (0.25 + 0.25) * 9 * sp * cT if fp32 else 0.0
+    columns = 13 * rowfield + 20 * rowfield + (1.0 + 0.75 + 0.75 + 0.25) * state + 6 * sp * cT + comp
     return {"rows_dyn": rows_dyn, "rows_rhs": rows_rhs, "columns": columns}
 
 

@@ -81,9 +81,12 @@ typedef enum { LM_FP64 = 0, LM_FP32_MIXED = 1 } lm_precision;
 typedef struct {
   int32_t n;           /* grid points per side: 64, 128, 192, 256, 384, 512 or 1024 */
   int32_t precision;   /* LM_FP64: everything float64.  LM_FP32_MIXED: transforms,
-                          products and gathers in float32; the xi and P state, their
-                          RK4 accumulators and the end-of-interval outputs (division
-                          by T included) in float64 */
+                          products, gathers and RK4 accumulators in float32; the other
+                          prognostic state (u, v, h and the g-bar, g-tilde and Eulerian
+                          accumulators) as compensated float32 pairs (a leading and a
+                          trailing word, renormalised at each step's update); the xi and
+                          P state, their RK4 accumulators and the end-of-interval outputs
+                          (division by T included) in float64 */
   double f, g, H;      /* Coriolis parameter, gravity, mean depth */
   double dt;           /* time step (shared by dynamics and mean PDEs) */
   double nu8;          /* eighth-order hyperviscosity on u, v, h (>= 0) */

@@ -83,8 +83,14 @@ __global__ void __launch_bounds__(col_threads<N>())
     const size_t j = col + (size_t)(ky + d.K);
     cplx<double> v = out[r];
     if (cx.kx == 0 && ky == 0) v.y = 0.0;
-    if (J.dst_f32[q]) reinterpret_cast<cplx<float>*>(J.dst[q])[j] = {float(v.x), float(v.y)};
-    else reinterpret_cast<cplx<double>*>(J.dst[q])[j] = v;
+    if (J.dst_f32[q]) {
+      const cplx<float> hi = {float(v.x), float(v.y)};
+      reinterpret_cast<cplx<float>*>(J.dst[q])[j] = hi;
+      if (J.dst_lo[q])
+        reinterpret_cast<cplx<float>*>(J.dst_lo[q])[j] = {float(v.x - double(hi.x)), float(v.y - double(hi.y))};
+    } else {
+      reinterpret_cast<cplx<double>*>(J.dst[q])[j] = v;
+    }
   }
 }
 
@@ -118,6 +124,10 @@ __global__ void __launch_bounds__(col_threads<N>())
     if (J.src_f32[q]) {
       const cplx<float> s = reinterpret_cast<const cplx<float>*>(J.src[q])[j];
       S[r] = {double(s.x), double(s.y)};
+      if (J.src_lo[q]) {
+        const cplx<float> l = reinterpret_cast<const cplx<float>*>(J.src_lo[q])[j];
+        S[r] = {S[r].x + double(l.x), S[r].y + double(l.y)};
+      }
     } else {
       S[r] = reinterpret_cast<const cplx<double>*>(J.src[q])[j];
     }

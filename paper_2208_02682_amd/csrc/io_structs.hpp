@@ -16,10 +16,12 @@ struct IoRowFwd {  // two physical fields -> two half-spectrum row fields
 struct IoColFwd {  // row-spectrum field -> normalised, truncated state
   const cplx<double>* src[IO_MAX];
   void* dst[IO_MAX];
+  void* dst_lo[IO_MAX];  // float state: trailing words (value - leading word), or null
   int dst_f32[IO_MAX];
 };
 struct IoColInv {  // truncated state -> column-pass output
   const void* src[IO_MAX];
+  const void* src_lo[IO_MAX];  // float state: trailing words added to the leading ones, or null
   int src_f32[IO_MAX];
   cplx<double>* dst[IO_MAX];
 };

@@ -153,16 +153,29 @@ namespace {
 // the launches of a run follow the table's schedule of its (N, precision)
 void use_sched(lm_run* r) { r->sched = get_sched(r->d.N, r->fp32, false); }
 
-// state field -> (pointer, is_float32)
-std::pair<const void*, int> state_field(lm_run* r, int which) {
+// one prognostic field's storage: leading words, trailing words of a
+// compensated float field (else null), and whether it is float
+struct FieldRef {
+  const void* ptr;
+  const void* lo;
+  int f32;
+};
+
+// working-precision state field sf (lm::StateField)
+FieldRef real_field(lm_run* r, int sf) {
   const size_t sp = r->d.spec_elems();
   const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  return {r->slab + r->L.Yr + sf * sp * cT, r->fp32 ? r->slab + r->L.Yl + sf * sp * cT : nullptr,
+          r->fp32 ? 1 : 0};
+}
+
+FieldRef state_field(lm_run* r, int which) {
   static const int rmap[9] = {lm::SF_U, lm::SF_V, lm::SF_H, lm::SF_GBH, lm::SF_GBZ,
                               lm::SF_GTH, lm::SF_GTZ, lm::SF_EH, lm::SF_EZ};
-  if (which >= LM_P_U && which <= LM_P_E_ZETA)
-    return {r->slab + r->L.Yr + rmap[which] * sp * cT, r->fp32 ? 1 : 0};
+  if (which >= LM_P_U && which <= LM_P_E_ZETA) return real_field(r, rmap[which]);
+  const size_t sp = r->d.spec_elems();
   static const int dmap[4] = {lm::SD_XIX, lm::SD_XIY, lm::SD_PX, lm::SD_PY};
-  return {r->slab + r->L.Yd + dmap[which - LM_P_XI_X] * sp * sizeof(cplx<double>), 0};
+  return {r->slab + r->L.Yd + dmap[which - LM_P_XI_X] * sp * sizeof(cplx<double>), nullptr, 0};
 }
 
 lm_status copy_in(lm_run* r, double* dst, const double* src, int on_device) {
@@ -181,6 +194,8 @@ lm_status zero_means(lm_run* r) {
   const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
   const int nsf = r->mom ? lm::NSF_R : lm::SF_GMX;
   HIP_TRY(hipMemsetAsync(r->slab + r->L.Yr + lm::SF_GBH * sp * cT, 0, (nsf - lm::SF_GBH) * sp * cT, r->stream));
+  if (r->fp32)
+    HIP_TRY(hipMemsetAsync(r->slab + r->L.Yl + lm::SF_GBH * sp * cT, 0, (nsf - lm::SF_GBH) * sp * cT, r->stream));
   HIP_TRY(hipMemsetAsync(r->slab + r->L.Yd, 0, lm::NSF_D * sp * sizeof(cplx<double>), r->stream));
   return LM_OK;
 }
@@ -295,6 +310,7 @@ lm_status lm_set_state(lm_run* r, const double* u, const double* v, const double
   for (int q = 0; q < 3; ++q) {
     K.src[q] = ioC + q * rf;
     K.dst[q] = r->slab + r->L.Yr + q * sp * cT;  // SF_U, SF_V, SF_H are 0, 1, 2
+    K.dst_lo[q] = r->fp32 ? r->slab + r->L.Yl + q * sp * cT : nullptr;
     K.dst_f32[q] = r->fp32 ? 1 : 0;
   }
   LM_DISPATCH_N(r->d.N, lm::launch_io_col_forward, *r, K, 3);
@@ -318,9 +334,10 @@ lm_status lm_get_state(lm_run* r, double* u, double* v, double* h, int on_device
   double* phys = (double*)r->at(r->L.phys);
   lm::IoColInv J{};
   for (int q = 0; q < 3; ++q) {
-    auto f = state_field(r, LM_P_U + q);
-    J.src[q] = f.first;
-    J.src_f32[q] = f.second;
+    const FieldRef f = state_field(r, LM_P_U + q);
+    J.src[q] = f.ptr;
+    J.src_lo[q] = f.lo;
+    J.src_f32[q] = f.f32;
     J.dst[q] = ioC + q * rf;
   }
   LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, J, 3);
@@ -393,9 +410,10 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
   for (int half = 0; half < 2; ++half) {
     lm::IoColInv J{};
     for (int q = 0; q < 5; ++q) {
-      auto f = state_field(r, order[half * 5 + q]);
-      J.src[q] = f.first;
-      J.src_f32[q] = f.second;
+      const FieldRef f = state_field(r, order[half * 5 + q]);
+      J.src[q] = f.ptr;
+      J.src_lo[q] = f.lo;
+      J.src_f32[q] = f.f32;
       J.dst[q] = ioC + (half * 5 + q) * rf;
     }
     LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, J, 5);
@@ -416,11 +434,11 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
   if (r->mom) {
     // the momentum 1-form mean g-bar_m / T (planes OUT_MOM, OUT_MOM + 1)
     lm::IoColInv Jm{};
-    const size_t sp = r->d.spec_elems();
-    const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
     for (int q = 0; q < 2; ++q) {
-      Jm.src[q] = r->slab + r->L.Yr + (lm::SF_GMX + q) * sp * cT;
-      Jm.src_f32[q] = r->fp32 ? 1 : 0;
+      const FieldRef f = real_field(r, lm::SF_GMX + q);
+      Jm.src[q] = f.ptr;
+      Jm.src_lo[q] = f.lo;
+      Jm.src_f32[q] = f.f32;
       Jm.dst[q] = ioC + q * rf;
     }
     LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, Jm, 2);
@@ -512,9 +530,10 @@ lm_status lm_peek(lm_run* r, int32_t which, double* out_, int on_device) {
   cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
   double* phys = (double*)r->at(r->L.phys);
   lm::IoColInv J{};
-  auto f = state_field(r, which);
-  J.src[0] = f.first;
-  J.src_f32[0] = f.second;
+  const FieldRef f = state_field(r, which);
+  J.src[0] = f.ptr;
+  J.src_lo[0] = f.lo;
+  J.src_f32[0] = f.f32;
   J.dst[0] = ioC;
   LM_DISPATCH_N(r->d.N, lm::launch_io_col_inverse, *r, J, 1);
   lm::IoRowInv K{};

@@ -28,7 +28,7 @@ constexpr int OUT_MOM = 14;  // momentum 1-form mean x, y (planes 14, 15), when 
 
 // byte offsets of every buffer inside the slab
 struct Layout {
-  size_t Yr, Yd, Ar, Ad, Ys0, Ys1, IC, RS, uvhz, tw64, twT, out, phys, ioC, flag, resid, total;
+  size_t Yr, Yl, Yd, Ar, Ad, Ys0, Ys1, IC, RS, uvhz, tw64, twT, out, phys, ioC, flag, resid, total;
 };
 
 // mom: also room for the strategy-2 mean of the momentum 1-form (its state,
@@ -46,6 +46,8 @@ inline Layout make_layout(const Dims& d, bool fp32, bool mom) {
   };
   const int nsf = mom ? NSF_R : SF_GMX, nic = mom ? NIC : IC_GMX, nrs = mom ? NRS : RS_GMX;
   L.Yr = take(nsf * sp * cT);
+  // float state is carried in two words (leading in Yr, trailing here)
+  L.Yl = take(fp32 ? nsf * sp * cT : 0);
   L.Yd = take(NSF_D * sp * cD);
   L.Ar = take(nsf * sp * cT);
   L.Ad = take(NSF_D * sp * cD);
@@ -92,6 +94,7 @@ template <typename T>
 StepPtrs<T> step_ptrs(RunView& r) {
   StepPtrs<T> P;
   P.Yr = (cplx<T>*)r.at(r.L.Yr);
+  P.Yl = std::is_same<T, float>::value ? (cplx<T>*)r.at(r.L.Yl) : nullptr;
   P.Yd = (cplx<double>*)r.at(r.L.Yd);
   P.Ar = (cplx<T>*)r.at(r.L.Ar);
   P.Ad = (cplx<double>*)r.at(r.L.Ad);

@@ -14,6 +14,7 @@ struct alignas(4 * sizeof(T)) P4 {
 template <typename T>
 struct StepPtrs {
   cplx<T>* Yr;        // [NSF_R][NKX][NKY] state, working precision
+  cplx<T>* Yl;        // same shape: trailing words of compensated float state (unused in float64)
   cplx<double>* Yd;   // [NSF_D][NKX][NKY] state, float64
   cplx<T>* Ar;        // RK4 accumulators, same shapes
   cplx<double>* Ad;

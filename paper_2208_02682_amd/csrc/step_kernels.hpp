@@ -573,10 +573,30 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_mom(StepPtrs<T> P, Dims
 template <typename TS>
 __device__ __forceinline__ cplx<TS> cadd(cplx<TS> a, cplx<TS> b) { return {a.x + b.x, a.y + b.y}; }
 
-// classical RK4: returns the next stage input (the new state after stage 3)
+// (hi, lo) + d for a float value carried as two words: Knuth's two-sum of hi
+// and d gives the sum and its exact rounding error, which is folded into lo
+// before the pair is renormalised (|lo| <= half an ulp of hi).  Contraction to
+// fused multiply-adds is off here: the error terms need the plain roundings.
+__device__ __forceinline__ void comp_add(float& hi, float& lo, float d) {
+#pragma clang fp contract(off)
+  const float s = hi + d;
+  const float bp = s - hi;
+  const float err = (hi - (s - bp)) + (d - bp);
+  const float t = lo + err;
+  const float h2 = s + t;
+  lo = t - (h2 - s);
+  hi = h2;
+}
+
+// classical RK4: returns the next stage input (the new state after stage 3).
+// Float state is compensated: Yp holds the leading word and Lp the trailing
+// one, so the state itself carries about 48 significant bits and the rounding
+// of the state at every step no longer accumulates over a long run.  Stage
+// inputs, right-hand sides and the accumulator Ap stay float (their rounding
+// enters once per step, scaled by dt).  Float64 state ignores Lp.
 template <typename TS>
-__device__ __forceinline__ cplx<TS> rk4(int stage, cplx<TS>* __restrict__ Yp, cplx<TS>* __restrict__ Ap,
-                                        cplx<TS> k, double dt) {
+__device__ __forceinline__ cplx<TS> rk4(int stage, cplx<TS>* __restrict__ Yp, cplx<TS>* __restrict__ Lp,
+                                        cplx<TS>* __restrict__ Ap, cplx<TS> k, double dt) {
   const cplx<TS> y = *Yp;
   if (stage == 0) {
     *Ap = k;
@@ -590,9 +610,18 @@ __device__ __forceinline__ cplx<TS> rk4(int stage, cplx<TS>* __restrict__ Yp, cp
   } else {
     const cplx<TS> a = *Ap;
     const TS c = TS(dt / 6.0);
-    const cplx<TS> yn = {y.x + c * (a.x + k.x), y.y + c * (a.y + k.y)};
-    *Yp = yn;
-    return yn;
+    if constexpr (std::is_same<TS, float>::value) {
+      cplx<TS> hi = y, lo = *Lp;
+      comp_add(hi.x, lo.x, c * (a.x + k.x));
+      comp_add(hi.y, lo.y, c * (a.y + k.y));
+      *Yp = hi;
+      *Lp = lo;
+      return hi;
+    } else {
+      const cplx<TS> yn = {y.x + c * (a.x + k.x), y.y + c * (a.y + k.y)};
+      *Yp = yn;
+      return yn;
+    }
   }
 }
 
@@ -714,6 +743,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
 
   // state of this group
   cplx<TS>* Y;
+  cplx<TS>* YL = nullptr;  // trailing words of compensated float state
   cplx<TS>* A;
   if constexpr (DBL) {
     constexpr int sd = (G == CG_XIX) ? SD_XIX : (G == CG_XIY) ? SD_XIY : (G == CG_PX) ? SD_PX : SD_PY;
@@ -724,6 +754,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
                      : (G == CG_GBZ) ? SF_GBZ : (G == CG_GTH) ? SF_GTH : (G == CG_GTZ) ? SF_GTZ
                      : (G == CG_GMX) ? SF_GMX : SF_GMY;
     Y = reinterpret_cast<cplx<TS>*>(P.Yr) + sr * sp;
+    if constexpr (std::is_same<TS, float>::value) YL = reinterpret_cast<cplx<TS>*>(P.Yl) + sr * sp;
     A = reinterpret_cast<cplx<TS>*>(P.Ar) + sr * sp;
   }
   const size_t col = (size_t)cx.kx * d.NKY;
@@ -769,17 +800,18 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
       R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
       // Eulerian accumulators: dE_eta/dt = eta (h less H at k = 0), dE_zeta/dt = i kx v - i ky u
       cplx<T>* Yr = P.Yr;
+      cplx<T>* Yl = P.Yl;
       cplx<T>* Ar = P.Ar;
       cplx<T> eta = h;
       if (cx.kx == 0 && ky == 0) eta.x -= HT;
-      rk4<T>(stage, Yr + SF_EH * sp + j, Ar + SF_EH * sp + j, eta, ph.dt);
+      rk4<T>(stage, Yr + SF_EH * sp + j, Yl + SF_EH * sp + j, Ar + SF_EH * sp + j, eta, ph.dt);
       const cplx<T> zeta = {-kxT * v.y + kyT * u.y, kxT * v.x - kyT * u.x};
-      rk4<T>(stage, Yr + SF_EZ * sp + j, Ar + SF_EZ * sp + j, zeta, ph.dt);
+      rk4<T>(stage, Yr + SF_EZ * sp + j, Yl + SF_EZ * sp + j, Ar + SF_EZ * sp + j, zeta, ph.dt);
     } else {
       R = r0[r];
     }
     const cplx<TS> Rk = {TS(R.x), TS(R.y)};
-    S[r] = rk4<TS>(stage, Y + j, A + j, Rk, ph.dt);
+    S[r] = rk4<TS>(stage, Y + j, YL + j, A + j, Rk, ph.dt);
     if constexpr (G == CG_U || G == CG_V || G == CG_H) Ys_out[(G - CG_U) * sp + j] = S[r];
   }
 
