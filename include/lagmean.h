@@ -61,11 +61,19 @@ typedef enum {
 
 typedef enum { LM_FP64 = 0, LM_FP32_MIXED = 1 } lm_precision;
 
-/* averaged fields (bit mask); the library averages h and zeta, and on request
-   the momentum 1-form u . dx with strategy 2 (appendix C) */
+/* averaged fields (bit mask).  Two scalar fields are averaged, by default h and
+   zeta; any other two of the five below may be chosen instead (the tests use
+   u, v and the potential vorticity q, which is materially conserved without
+   dissipation: section 4.1, eq. (4.2), and the potential-vorticity argument of
+   section 4.2.1).  The two fields fill the output slots field = 0 and 1 in the
+   order of their bits (lowest first).  On request strategy 2 also averages the
+   momentum 1-form u . dx (appendix C). */
 #define LM_F_H 1u
 #define LM_F_ZETA 2u
 #define LM_F_MOMENTUM 4u
+#define LM_F_U 8u
+#define LM_F_V 16u
+#define LM_F_Q 32u /* (f + zeta) / h */
 /* strategies (bit mask); the library always integrates all three */
 #define LM_S1 1u
 #define LM_S2 2u
@@ -76,7 +84,9 @@ typedef enum { LM_FP64 = 0, LM_FP32_MIXED = 1 } lm_precision;
                                 points; the paper compares linear and cubic
                                 interpolation for strategy 1, section 4.1) */
 /* driver of u, v, h */
-#define LM_DYNAMIC 0
+#define LM_DYNAMIC 0              /* the rotating shallow-water equations */
+#define LM_KINEMATIC_PLANEWAVE 1  /* prescribed, for tests: a linear Poincare plane
+                                     wave plus a uniform flow (kin[] below) */
 
 typedef struct {
   int32_t n;           /* grid points per side: 64, 128, 192, 256, 384, 512 or 1024 */
@@ -90,7 +100,10 @@ typedef struct {
   double f, g, H;      /* Coriolis parameter, gravity, mean depth */
   double dt;           /* time step (shared by dynamics and mean PDEs) */
   double nu8;          /* eighth-order hyperviscosity on u, v, h (>= 0) */
-  uint32_t avg_fields; /* LM_F_H | LM_F_ZETA (or 0 for the default), optionally | LM_F_MOMENTUM:
+  uint32_t avg_fields; /* two of LM_F_H, LM_F_ZETA, LM_F_U, LM_F_V, LM_F_Q (0: LM_F_H | LM_F_ZETA),
+                          optionally | LM_F_MOMENTUM.  Averaging fields other than
+                          (h, zeta) takes two more forward transforms per stage for
+                          their Eulerian means.  LM_F_MOMENTUM:
                           strategy 2 also integrates the mean of the momentum 1-form,
                           eq. (C.4) in the g-bar form of eq. (4.5b):
                           dg_i/dt + w_j d_j g_i + g_j d_i w_j = u_j(x + xi)(delta_ij + d_i xi_j)
@@ -98,7 +111,22 @@ typedef struct {
                           column groups; a larger footprint) */
   uint32_t strategies; /* must be LM_S1 | LM_S2 | LM_EULER (or 0 for the default) */
   int32_t interp;      /* LM_INTERP_BILINEAR or LM_INTERP_CUBIC */
-  int32_t mode;        /* LM_DYNAMIC */
+  int32_t mode;        /* LM_DYNAMIC or LM_KINEMATIC_PLANEWAVE */
+  double kin[8];       /* LM_KINEMATIC_PLANEWAVE only (ignored otherwise): the prescribed
+                          flow at time t (t = 0 at lm_create, steps * dt after) is
+                            h = H + A cos(theta), theta = kx x + ky y - omega t + phase,
+                            u = U0 + A (omega kx cos(theta) - f ky sin(theta)) / (H |k|^2),
+                            v = V0 + A (omega ky cos(theta) + f kx sin(theta)) / (H |k|^2),
+                          the linear plane wave of section 4.2.1, eq. (4.8), in any
+                          direction; for A < H the particle phase obeys an Adler
+                          equation with a real frequency, and over whole periods of it
+                          the Lagrangian means are constants known in closed form.
+                          kin = {kx, ky, A, omega (0: the dispersion relation
+                          omega^2 = f^2 + g H |k|^2), phase, U0, V0, unused}.  kx, ky
+                          integers inside the 2/3-rule mask (else LM_E_ARG); A = 0 gives
+                          the uniform flow alone.  Such a run has no lm_set_state
+                          (LM_E_STATE); its state is defined from lm_create on, and
+                          lm_get_state returns the prescribed u, v, h at the current time */
 } lm_config;
 
 typedef struct lm_run lm_run;
@@ -164,7 +192,9 @@ typedef enum {
                              created with LM_F_MOMENTUM; else LM_E_STATE)     */
   LM_K_S2_MOM_Y = 11      /* same, y component                               */
 } lm_kind;
-typedef enum { LM_FIELD_H = 0, LM_FIELD_ZETA = 1 } lm_field;
+/* output slot of a scalar averaged field: the first (lowest bit) or second of
+   the two averaged fields; with the default fields, h and zeta */
+typedef enum { LM_FIELD_H = 0, LM_FIELD_ZETA = 1, LM_FIELD_FIRST = 0, LM_FIELD_SECOND = 1 } lm_field;
 
 /* Remap the strategy-1 outputs of the last closed interval to Lagrangian-mean
    positions (section 3.1, eq. (3.8): f~^L(x) = f-bar^L(Xi^{-1}(x))).  For every
@@ -364,6 +394,15 @@ lm_status lm_e2d_end_interval(lm_e2d* e, double* T_out);
 lm_status lm_e2d_read(lm_e2d* e, int32_t kind, double* out, int on_device);
 /* Release (waits for the stream).  Null is a no-op. */
 lm_status lm_e2d_destroy(lm_e2d* e);
+
+/* HIP versions, as major * 10^7 + minor * 10^5 + patch: *built receives that of
+   the HIP headers the library was compiled with, *runtime that of the HIP
+   runtime this process has bound (hipRuntimeGetVersion).  The library binds the
+   HIP runtime already loaded in the process when there is one (PyTorch ships
+   its own copy, with the same soname); otherwise the one it was built with.
+   The two may differ; callers that care compare them.  Either pointer may be
+   null.  LM_E_HIP if the runtime cannot report its version. */
+lm_status lm_hip_versions(int32_t* built, int32_t* runtime);
 
 /* Text of a status code (static storage). */
 const char* lm_status_str(lm_status s);

@@ -26,7 +26,19 @@ def cache_path(arch: str) -> str:
 
 
 def device_arch() -> str:
-    """Architecture name of device 0 (e.g. gfx950), from the runtime's properties."""
+    """Architecture name of the first GPU (e.g. gfx950), from the kernel driver's
+    topology (host only: no HIP call, so it works in processes without torch),
+    else from torch's device properties."""
+    import glob
+    for props in sorted(glob.glob("/sys/class/kfd/kfd/topology/nodes/*/properties")):
+        try:
+            with open(props) as f:
+                kv = dict(line.split()[:2] for line in f if len(line.split()) >= 2)
+        except OSError:
+            continue
+        v = int(kv.get("gfx_target_version", "0"))
+        if v > 0:  # major * 10000 + minor * 100 + stepping; CPU nodes report 0
+            return f"gfx{v // 10000}{(v // 100) % 100:x}{v % 100:x}"
     import torch
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 

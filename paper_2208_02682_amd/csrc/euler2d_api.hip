@@ -247,6 +247,7 @@ lm_status lm_e2d_set_vorticity(lm_e2d* e, const double* zeta, int on_device) {
   lm::RunView& v = e->v;
   const lm::Dims& d = v.d;
   const size_t sp = d.spec_elems(), rf = d.rowfield_elems(), nn = (size_t)d.N * d.N;
+  const lm::StreamDrain drain{v.stream};  // the caller's buffer is read before any return
   double* PH = e->at<double>(e->PH);
   HIP_TRY(hipMemcpyAsync(PH, zeta, nn * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                          v.stream));
@@ -332,6 +333,7 @@ lm_status lm_e2d_end_interval(lm_e2d* e, double* T_out) {
   const lm::Dims& d = v.d;
   const size_t sp = d.spec_elems(), rf = d.rowfield_elems(), nn = (size_t)d.N * d.N;
   const double T = double(e->n - e->n_tau) * e->dt;
+  const lm::StreamDrain drain{v.stream};
   cplx<double>* IC = e->at<cplx<double>>(e->IC);
   double* OUT = e->at<double>(e->OUT);
   lm::IoColInv J{};
@@ -369,6 +371,7 @@ lm_status lm_e2d_read(lm_e2d* e, int32_t kind, double* out, int on_device) {
   if (!e || !out) return fail(LM_E_ARG, "null argument");
   if (kind < LM_E2D_ZETA || kind > LM_E2D_SL_ETA_Y) return fail(LM_E_ARG, "unknown kind");
   if (!e->has_out) return fail(LM_E_STATE, "no closed interval");
+  const lm::StreamDrain drain{e->v.stream};  // the caller's buffer is written before any return
   const size_t nn = (size_t)e->v.d.N * e->v.d.N;
   HIP_TRY(hipMemcpyAsync(out, e->at<double>(e->OUT) + kind * nn, nn * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, e->v.stream));

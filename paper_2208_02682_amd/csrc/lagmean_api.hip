@@ -47,15 +47,67 @@ lm_status check_cfg(const lm_config* cfg) {
   if (!(cfg->nu8 >= 0.0) || !std::isfinite(cfg->nu8)) return fail(LM_E_ARG, "nu8 must be >= 0");
   if (!std::isfinite(cfg->f) || !std::isfinite(cfg->g) || !std::isfinite(cfg->H))
     return fail(LM_E_ARG, "f, g, H must be finite");
-  if (cfg->avg_fields != 0 && cfg->avg_fields != (LM_F_H | LM_F_ZETA) &&
-      cfg->avg_fields != (LM_F_H | LM_F_ZETA | LM_F_MOMENTUM))
-    return fail(LM_E_UNSUPPORTED, "averaged fields are h and zeta, optionally with the momentum 1-form");
+  {
+    const uint32_t f = cfg->avg_fields & ~LM_F_MOMENTUM;
+    const uint32_t known = LM_F_H | LM_F_ZETA | LM_F_U | LM_F_V | LM_F_Q;
+    if ((f & ~known) != 0 || (f != 0 && __builtin_popcount(f) != 2))
+      return fail(LM_E_UNSUPPORTED, "averaged fields: two of LM_F_H, LM_F_ZETA, LM_F_U, LM_F_V, LM_F_Q (or 0), "
+                                    "optionally with LM_F_MOMENTUM");
+  }
   if (cfg->strategies != 0 && cfg->strategies != (LM_S1 | LM_S2 | LM_EULER))
     return fail(LM_E_UNSUPPORTED, "all of strategy 1, strategy 2 and the Eulerian mean are integrated");
   if (cfg->interp != LM_INTERP_BILINEAR && cfg->interp != LM_INTERP_CUBIC)
     return fail(LM_E_UNSUPPORTED, "interp must be LM_INTERP_BILINEAR or LM_INTERP_CUBIC");
-  if (cfg->mode != LM_DYNAMIC) return fail(LM_E_UNSUPPORTED, "dynamic mode only");
+  if (cfg->mode != LM_DYNAMIC && cfg->mode != LM_KINEMATIC_PLANEWAVE)
+    return fail(LM_E_UNSUPPORTED, "mode must be LM_DYNAMIC or LM_KINEMATIC_PLANEWAVE");
+  if (cfg->mode == LM_KINEMATIC_PLANEWAVE) {
+    for (int i = 0; i < 7; ++i)
+      if (!std::isfinite(cfg->kin[i])) return fail(LM_E_ARG, "kin[] must be finite");
+    const double kx = cfg->kin[0], ky = cfg->kin[1];
+    const int K = (cfg->n - 1) / 3;
+    if (kx != std::floor(kx) || ky != std::floor(ky) || std::fabs(kx) > K || std::fabs(ky) > K)
+      return fail(LM_E_ARG, "kin: the wave vector must be integer and inside the 2/3-rule mask");
+    if (!(cfg->H > 0.0)) return fail(LM_E_ARG, "kin: H must be positive");
+    if (cfg->kin[2] != 0.0 && kx == 0.0 && ky == 0.0) return fail(LM_E_ARG, "kin: a wave needs a wave vector");
+  }
   return LM_OK;
+}
+
+// the two averaged fields (lowest mask bit first) as lm::FieldSel
+void field_slots(uint32_t mask, int* fs0, int* fs1) {
+  uint32_t f = mask & ~LM_F_MOMENTUM;
+  if (f == 0) f = LM_F_H | LM_F_ZETA;
+  static const uint32_t bit[5] = {LM_F_H, LM_F_ZETA, LM_F_U, LM_F_V, LM_F_Q};
+  static const int sel[5] = {lm::FS_ETA, lm::FS_ZETA, lm::FS_U, lm::FS_V, lm::FS_Q};
+  int k = 0;
+  for (int i = 0; i < 5; ++i)
+    if (f & bit[i]) (k++ == 0 ? *fs0 : *fs1) = sel[i];
+}
+
+// physics constants and launch flags of a valid configuration
+lm::Phys make_phys(const lm_config* cfg) {
+  lm::Phys ph{};
+  ph.f = cfg->f;
+  ph.g = cfg->g;
+  ph.H = cfg->H;
+  ph.dt = cfg->dt;
+  ph.nu8 = cfg->nu8;
+  field_slots(cfg->avg_fields, &ph.fs0, &ph.fs1);
+  ph.gen = !(ph.fs0 == lm::FS_ETA && ph.fs1 == lm::FS_ZETA);
+  ph.mom = (cfg->avg_fields & LM_F_MOMENTUM) != 0;
+  ph.kin = cfg->mode == LM_KINEMATIC_PLANEWAVE;
+  if (ph.kin) {
+    ph.kx = cfg->kin[0];
+    ph.ky = cfg->kin[1];
+    ph.A = cfg->kin[2];
+    // omega = 0 asks for the Poincare dispersion relation
+    ph.omega = cfg->kin[3] != 0.0 ? cfg->kin[3]
+                                  : std::sqrt(cfg->f * cfg->f + cfg->g * cfg->H * (ph.kx * ph.kx + ph.ky * ph.ky));
+    ph.phase = cfg->kin[4];
+    ph.U0 = cfg->kin[5];
+    ph.V0 = cfg->kin[6];
+  }
+  return ph;
 }
 
 // ---------------------------------------------------------------------------
@@ -130,6 +182,7 @@ struct lm_batch {
     bool fp32;
     bool cubic;
     bool mom;
+    bool gen;  // Eulerian means of fields other than (h, zeta): two more column groups
     void* d_desc = nullptr;  // device array of RunDesc<T>
     size_t cap = 0;          // bytes
     hipStream_t fork = nullptr;
@@ -172,6 +225,14 @@ FieldRef real_field(lm_run* r, int sf) {
 FieldRef state_field(lm_run* r, int which) {
   static const int rmap[9] = {lm::SF_U, lm::SF_V, lm::SF_H, lm::SF_GBH, lm::SF_GBZ,
                               lm::SF_GTH, lm::SF_GTZ, lm::SF_EH, lm::SF_EZ};
+  if (r->ph.kin && which >= LM_P_U && which <= LM_P_H) {
+    // a prescribed flow has no u, v, h state: its values at the current time
+    // are the current stage input
+    const size_t sp = r->d.spec_elems();
+    const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+    const size_t ys = r->ys_cur ? r->L.Ys1 : r->L.Ys0;
+    return {r->slab + ys + (which - LM_P_U) * sp * cT, nullptr, r->fp32 ? 1 : 0};
+  }
   if (which >= LM_P_U && which <= LM_P_E_ZETA) return real_field(r, rmap[which]);
   const size_t sp = r->d.spec_elems();
   static const int dmap[4] = {lm::SD_XIX, lm::SD_XIY, lm::SD_PX, lm::SD_PY};
@@ -199,6 +260,8 @@ lm_status zero_means(lm_run* r) {
   HIP_TRY(hipMemsetAsync(r->slab + r->L.Yd, 0, lm::NSF_D * sp * sizeof(cplx<double>), r->stream));
   return LM_OK;
 }
+
+using lm::StreamDrain;
 
 lm_status check_launch() {
   hipError_t e = hipGetLastError();
@@ -231,12 +294,23 @@ const char* lm_status_str(lm_status s) {
 
 const char* lm_last_error(void) { return g_err.c_str(); }
 
+lm_status lm_hip_versions(int32_t* built, int32_t* runtime) {
+  if (built) *built = (int32_t)HIP_VERSION;
+  if (runtime) {
+    int v = 0;
+    const hipError_t e = hipRuntimeGetVersion(&v);
+    if (e != hipSuccess) return fail(LM_E_HIP, std::string("hipRuntimeGetVersion: ") + hipGetErrorString(e));
+    *runtime = (int32_t)v;
+  }
+  return LM_OK;
+}
+
 lm_status lm_query_footprint(const lm_config* cfg, size_t* bytes) {
   lm_status s = check_cfg(cfg);
   if (s != LM_OK) return s;
   if (!bytes) return fail(LM_E_ARG, "null bytes");
-  *bytes = lm::make_layout(lm::Dims::make(cfg->n), cfg->precision == LM_FP32_MIXED,
-                           (cfg->avg_fields & LM_F_MOMENTUM) != 0).total;
+  const lm::Phys ph = make_phys(cfg);
+  *bytes = lm::make_layout(lm::Dims::make(cfg->n), cfg->precision == LM_FP32_MIXED, ph.mom, ph.gen).total;
   return LM_OK;
 }
 
@@ -248,12 +322,12 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
   lm_run* r = new lm_run();
   r->cfg = *cfg;
   r->d = lm::Dims::make(cfg->n);
-  r->ph = lm::Phys{cfg->f, cfg->g, cfg->H, cfg->dt, cfg->nu8};
+  r->ph = make_phys(cfg);
   r->stream = (hipStream_t)hip_stream;
   r->fp32 = cfg->precision == LM_FP32_MIXED;
   r->cubic = cfg->interp == LM_INTERP_CUBIC;
   r->mom = (cfg->avg_fields & LM_F_MOMENTUM) != 0;
-  r->L = lm::make_layout(r->d, r->fp32, r->mom);
+  r->L = lm::make_layout(r->d, r->fp32, r->mom, r->ph.gen);
   r->n = r->n_tau = 0;
   r->has_state = r->in_interval = r->has_mean = r->has_remap = false;
   r->T = 0.0;
@@ -280,7 +354,17 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
     e = r->fp32 ? hipMemcpy(r->slab + r->L.twT, twf.data(), N * sizeof(cplx<float>), hipMemcpyHostToDevice)
                 : hipMemcpy(r->slab + r->L.twT, tw.data(), N * sizeof(cplx<double>), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(r->slab, 0, r->L.tw64);
+  if (e == hipSuccess && r->ph.kin) {
+    // a prescribed flow is defined from the start (time 0): its column-pass
+    // outputs of the current time, as after lm_set_state
+    use_sched(r);
+    LM_DISPATCH_N(r->d.N, lm::launch_prologue, *r);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    r->has_state = (e == hipSuccess);
+  }
   if (e != hipSuccess) {
+    (void)hipStreamSynchronize(r->stream);
     (void)hipFree(r->slab);
     delete r;
     return fail(LM_E_HIP, std::string("init: ") + hipGetErrorString(e));
@@ -292,6 +376,8 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
 lm_status lm_set_state(lm_run* r, const double* u, const double* v, const double* h, int on_device) {
   if (!r || !u || !v || !h) return fail(LM_E_ARG, "null argument");
   if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
+  if (r->ph.kin) return fail(LM_E_STATE, "a kinematic run's flow is prescribed");
+  const StreamDrain drain{r->stream};  // the caller's buffers are read before any return
   const size_t nn = (size_t)r->d.N * r->d.N;
   double* phys = (double*)r->at(r->L.phys);
   lm_status s;
@@ -329,6 +415,7 @@ lm_status lm_set_state(lm_run* r, const double* u, const double* v, const double
 lm_status lm_get_state(lm_run* r, double* u, double* v, double* h, int on_device) {
   if (!r || !u || !v || !h) return fail(LM_E_ARG, "null argument");
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  const StreamDrain drain{r->stream};  // the caller's buffers are written before any return
   const size_t nn = (size_t)r->d.N * r->d.N, rf = r->d.rowfield_elems();
   cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
   double* phys = (double*)r->at(r->L.phys);
@@ -400,6 +487,7 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
   if (!r->in_interval) return fail(LM_E_STATE, "no open interval");
   if (r->n == r->n_tau) return fail(LM_E_STATE, "interval holds no step");
   const double T = double(r->n - r->n_tau) * r->ph.dt;
+  const StreamDrain drain{r->stream};
   const size_t nn = (size_t)r->d.N * r->d.N, rf = r->d.rowfield_elems();
   cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
   double* out = (double*)r->at(r->L.out);
@@ -427,7 +515,8 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
     const double sc = (p == 1) ? 1.0 : 1.0 / T;  // xi is not divided
     K.sa[p] = K.sb[p] = sc;
     // the h accumulators integrate eta = h - H: the mean of h is H + (mean of eta)
-    K.ca[p] = (p == 0 || p == 2 || p == 4) ? r->ph.H : 0.0;
+    // (h, when averaged, is always the first field)
+    K.ca[p] = ((p == 0 || p == 2 || p == 4) && r->ph.fs0 == lm::FS_ETA) ? r->ph.H : 0.0;
     K.cb[p] = 0.0;
   }
   LM_DISPATCH_N(r->d.N, lm::launch_io_row_inverse, *r, K, 5);
@@ -456,9 +545,10 @@ lm_status lm_end_interval(lm_run* r, double* T_out) {
   if (r->mom) lm::launch_nonfinite(*r, out + lm::OUT_MOM * nn, 2 * nn, flag);
   lm_status s;
   if ((s = check_launch()) != LM_OK) return s;
+  // the flag is read with a blocking copy once the stream has drained
   int hflag = 0;
-  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, r->stream));
   HIP_TRY(hipStreamSynchronize(r->stream));
+  HIP_TRY(hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost));
   r->T = T;
   r->has_mean = true;
   r->in_interval = false;
@@ -472,6 +562,7 @@ lm_status lm_remap_s1(lm_run* r, int32_t max_extent, double* residual) {
   if (max_extent < 1 || max_extent > 64) return fail(LM_E_ARG, "max_extent must be in 1..64");
   if (!r->has_mean) return fail(LM_E_STATE, "no closed interval");
   if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
+  const StreamDrain drain{r->stream};
   const size_t nn = (size_t)r->d.N * r->d.N;
   double* out = (double*)r->at(r->L.out);
   unsigned long long* bits = (unsigned long long*)r->at(r->L.resid);
@@ -484,8 +575,8 @@ lm_status lm_remap_s1(lm_run* r, int32_t max_extent, double* residual) {
   lm_status s;
   if ((s = check_launch()) != LM_OK) return s;
   unsigned long long hb = 0;
-  HIP_TRY(hipMemcpyAsync(&hb, bits, sizeof(hb), hipMemcpyDeviceToHost, r->stream));
   HIP_TRY(hipStreamSynchronize(r->stream));
+  HIP_TRY(hipMemcpy(&hb, bits, sizeof(hb), hipMemcpyDeviceToHost));
   double res;
   memcpy(&res, &hb, sizeof(res));
   r->has_remap = true;
@@ -516,6 +607,7 @@ lm_status lm_read_mean(lm_run* r, int32_t field, int32_t kind, double* out_, int
   if (idx >= lm::OUT_MOM && !r->mom) return fail(LM_E_STATE, "the run does not average the momentum 1-form");
   if (idx >= lm::OUT_REMAP && idx < lm::OUT_REMAP + 4 && !r->has_remap)
     return fail(LM_E_STATE, "no strategy-1 remap of the last interval");
+  const StreamDrain drain{r->stream};
   const size_t nn = (size_t)r->d.N * r->d.N;
   lm_status s = copy_out(r, out_, (double*)r->at(r->L.out) + idx * nn, on_device);
   if (s != LM_OK) return s;
@@ -527,6 +619,7 @@ lm_status lm_peek(lm_run* r, int32_t which, double* out_, int on_device) {
   if (!r || !out_) return fail(LM_E_ARG, "null argument");
   if (which < LM_P_U || which > LM_P_P_Y) return fail(LM_E_ARG, "unknown field");
   if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  const StreamDrain drain{r->stream};
   cplx<double>* ioC = (cplx<double>*)r->at(r->L.ioC);
   double* phys = (double*)r->at(r->L.phys);
   lm::IoColInv J{};
@@ -571,14 +664,15 @@ lm_status lm_destroy(lm_run* r) {
 // ---------------------------------------------------------------------------
 namespace {
 
-lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32, bool cubic, bool mom) {
+lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32, bool cubic, bool mom, bool gen) {
   for (auto& g : b->groups)
-    if (g.N == N && g.fp32 == fp32 && g.cubic == cubic && g.mom == mom) return &g;
+    if (g.N == N && g.fp32 == fp32 && g.cubic == cubic && g.mom == mom && g.gen == gen) return &g;
   lm_batch::Group g;
   g.N = N;
   g.fp32 = fp32;
   g.cubic = cubic;
   g.mom = mom;
+  g.gen = gen;
   if (hipStreamCreateWithFlags(&g.fork, hipStreamNonBlocking) != hipSuccess) return nullptr;
   if (hipEventCreateWithFlags(&g.join, hipEventDisableTiming) != hipSuccess) return nullptr;
   b->groups.push_back(g);
@@ -586,12 +680,11 @@ lm_batch::Group* batch_group(lm_batch* b, int N, bool fp32, bool cubic, bool mom
 }
 
 template <typename T>
-std::vector<char> group_descs(lm_batch* b, int N, bool fp32, bool cubic, bool mom, const std::vector<int>& active,
-                              int* count) {
+std::vector<char> group_descs(lm_batch* b, const lm_batch::Group& g, const std::vector<int>& active, int* count) {
   std::vector<lm::RunDesc<T>> d;
   for (int i : active) {
     lm_run* r = b->members[i].run;
-    if (r->d.N == N && r->fp32 == fp32 && r->cubic == cubic && r->mom == mom)
+    if (r->d.N == g.N && r->fp32 == g.fp32 && r->cubic == g.cubic && r->mom == g.mom && (bool)r->ph.gen == g.gen)
       d.push_back(lm::run_desc<T>(*r, b->d_counters + i));
   }
   *count = (int)d.size();
@@ -621,13 +714,13 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
   std::vector<Launch> launches;
   for (int i : active) {
     lm_run* r = b->members[i].run;
-    lm_batch::Group* g = batch_group(b, r->d.N, r->fp32, r->cubic, r->mom);
+    lm_batch::Group* g = batch_group(b, r->d.N, r->fp32, r->cubic, r->mom, r->ph.gen);
     if (!g) return fail(LM_E_HIP, "batch: stream or event creation failed");
   }
   for (auto& g : b->groups) {
     int count = 0;
-    std::vector<char> bytes = g.fp32 ? group_descs<float>(b, g.N, true, g.cubic, g.mom, active, &count)
-                                     : group_descs<double>(b, g.N, false, g.cubic, g.mom, active, &count);
+    std::vector<char> bytes = g.fp32 ? group_descs<float>(b, g, active, &count)
+                                     : group_descs<double>(b, g, active, &count);
     if (count == 0) continue;
     if (bytes.size() > g.cap) {
       if (g.d_desc) (void)hipFree(g.d_desc);
@@ -649,8 +742,11 @@ lm_status batch_rebuild(lm_batch* b, const std::vector<int>& active) {
     const Launch& l = launches[li];
     if (e == hipSuccess) e = hipStreamWaitEvent(l.g->fork, b->fork_ev, 0);
     if (e == hipSuccess) {
+      lm::Phys gp{};
+      gp.mom = l.g->mom;
+      gp.gen = l.g->gen;
       LM_DISPATCH_N(l.g->N, lm::launch_batch_step, l.g->fork, l.g->d_desc, l.count, l.g->fp32, l.g->cubic, l.g->mom,
-                    scheds[li]);
+                    lm::col_groups(gp), scheds[li]);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(l.g->join, l.g->fork);
@@ -720,9 +816,12 @@ lm_status lm_batch_remove(lm_batch* b, lm_run* r) {
   if (!b || !r) return fail(LM_E_ARG, "null argument");
   const int i = find_member(b, r);
   if (i < 0) return fail(LM_E_ARG, "not a member");
+  // no queued batch step may still write the run's buffers once it has left
+  const hipError_t e = hipStreamSynchronize(b->stream);
   b->members.erase(b->members.begin() + i);
   r->batch = nullptr;
   drop_graph(b);
+  if (e != hipSuccess) return fail(LM_E_HIP, std::string("batch remove: ") + hipGetErrorString(e));
   return LM_OK;
 }
 
@@ -773,6 +872,7 @@ extern "C" {
 lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
   if (!b) return fail(LM_E_ARG, "null batch");
   if (max_steps < 0) return fail(LM_E_ARG, "max_steps < 0");
+  const StreamDrain drain{b->stream};  // every path out leaves no batch step in flight
   const int m = (int)b->members.size();
   lm_status st = upload_counters(b);
   if (st != LM_OK) return st;

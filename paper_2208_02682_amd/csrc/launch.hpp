@@ -11,8 +11,9 @@ template <int N> void launch_steps(RunView& r, int nsteps);   // nsteps RK4 step
 template <int N> hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms);  // + kernel times
 template <int N> void launch_prologue(RunView& r);            // column pass of the current state
 // one RK4 step for nruns runs of one (N, precision, gather, momentum) group; desc: device array of RunDesc<T>
+// ncg: column groups per run (col_groups of the group's runs)
 template <int N> void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic, bool mom,
-                                        const Sched& sc);
+                                        int ncg, const Sched& sc);
 void launch_batch_tick(hipStream_t st, long long* counters, int n);  // counters[i] += 1
 template <int N> void launch_io_row_forward(RunView& r, const IoRowFwd& J, int count);
 template <int N> void launch_io_col_forward(RunView& r, const IoColFwd& J, int count);

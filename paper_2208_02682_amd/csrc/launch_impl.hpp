@@ -48,11 +48,15 @@ void launch_columns_t(RunView& r, int stage) {
   cplx<T>* Ys[2] = {(cplx<T>*)r.at(r.L.Ys0), (cplx<T>*)r.at(r.L.Ys1)};
   const cplx<T>* Ys_in = Ys[r.ys_cur];
   cplx<T>* Ys_out = (stage < 0) ? Ys[r.ys_cur] : Ys[r.ys_cur ^ 1];
-  const int groups = r.mom ? NCG_MOM : NCG;
+  const int groups = col_groups(r.ph);
+  // time of the stage input this launch prepares: the current one in the
+  // prologue, else the next stage's (c = 1/2, 1/2, 1, then the next step's 0)
+  const double t_next = (double(r.n) + (stage < 0 ? 0.0 : (stage <= 1 ? 0.5 : 1.0))) * r.ph.dt;
   with_tile<T, N>(r.sched.tile, [&](auto w) {
     constexpr int W = decltype(w)::value;
     const dim3 g = col_grid<N, W>(r.d, groups), b = col_block<N, W>();
-    hipLaunchKernelGGL((k_columns<T, N, W>), g, b, 0, r.stream, P, r.d, r.ph, stage, Ys_in, Ys_out, r.sched.remap);
+    hipLaunchKernelGGL((k_columns<T, N, W>), g, b, 0, r.stream, P, r.d, r.ph, stage, t_next, Ys_in, Ys_out,
+                       r.sched.remap);
   });
   if (stage >= 0) r.ys_cur ^= 1;
 }
@@ -80,7 +84,7 @@ void launch_steps_t(RunView& r, int nsteps) {
       // time since the interval start, from integers
       const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
       hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
-                         r.sched.remap);
+                         r.ph, r.sched.remap);
       launch_rows_rhs<T, N>(r, P, sval);
       launch_columns_t<T, N>(r, stage);
     }
@@ -115,7 +119,7 @@ hipError_t launch_steps_profiled_t(RunView& r, int nsteps, double* ms) {
       // interval covers one kernel's execution only
       (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
-                         r.sched.remap);
+                         r.ph, r.sched.remap);
       (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
       (void)hipEventRecord(ev[e++], r.stream);
@@ -148,7 +152,8 @@ hipError_t launch_steps_profiled(RunView& r, int nsteps, double* ms) {
 // one RK4 step of every run of one (N, precision) group: blockIdx.z selects
 // the run's descriptor
 template <typename T, int N>
-void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool cubic, bool mom, const Sched& sc) {
+void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool cubic, bool mom, int ncg,
+                         const Sched& sc) {
   const Dims d = Dims::make(N);
   const int rm = sc.remap;
   for (int stage = 0; stage < 4; ++stage) {
@@ -168,7 +173,7 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool
     }
     with_tile<T, N>(sc.tile, [&](auto w) {
       constexpr int W = decltype(w)::value;
-      dim3 g3 = col_grid<N, W>(d, mom ? NCG_MOM : NCG);
+      dim3 g3 = col_grid<N, W>(d, ncg);
       g3.z = nruns;
       const dim3 b3 = col_block<N, W>();
       hipLaunchKernelGGL((k_columns_b<T, N, W>), g3, b3, 0, st, desc, stage, rm);
@@ -177,10 +182,10 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool
 }
 
 template <int N>
-void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic, bool mom,
+void launch_batch_step(hipStream_t st, const void* desc, int nruns, bool fp32, bool cubic, bool mom, int ncg,
                        const Sched& sc) {
-  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns, cubic, mom, sc);
-  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns, cubic, mom, sc);
+  if (fp32) launch_batch_step_t<float, N>(st, (const RunDesc<float>*)desc, nruns, cubic, mom, ncg, sc);
+  else launch_batch_step_t<double, N>(st, (const RunDesc<double>*)desc, nruns, cubic, mom, ncg, sc);
 }
 
 template <int N>
@@ -227,7 +232,7 @@ void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
   template void launch_steps_t<T, N>(RunView&, int);                                                     \
   template hipError_t launch_steps_profiled_t<T, N>(RunView&, int, double*);                             \
   template void launch_columns_t<T, N>(RunView&, int);                                                   \
-  template void launch_batch_step_t<T, N>(hipStream_t, const RunDesc<T>*, int, bool, bool, const Sched&); \
+  template void launch_batch_step_t<T, N>(hipStream_t, const RunDesc<T>*, int, bool, bool, int, const Sched&); \
   }
 
 #define LM_EXTERN_T(T, N)                                                                                       \
@@ -235,7 +240,7 @@ void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
   extern template void launch_steps_t<T, N>(RunView&, int);                                                     \
   extern template hipError_t launch_steps_profiled_t<T, N>(RunView&, int, double*);                             \
   extern template void launch_columns_t<T, N>(RunView&, int);                                                   \
-  extern template void launch_batch_step_t<T, N>(hipStream_t, const RunDesc<T>*, int, bool, bool, const Sched&); \
+  extern template void launch_batch_step_t<T, N>(hipStream_t, const RunDesc<T>*, int, bool, bool, int, const Sched&); \
   }
 
 #define LM_INSTANTIATE(N)                                                                             \
@@ -243,7 +248,7 @@ void launch_io_col_forward(RunView& r, const IoColFwd& J, int count) {
   LM_EXTERN_T(double, N)                                                                              \
   namespace lm {                                                                                      \
   template void launch_steps<N>(RunView&, int);                                                       \
-  template void launch_batch_step<N>(hipStream_t, const void*, int, bool, bool, bool, const Sched&);  \
+  template void launch_batch_step<N>(hipStream_t, const void*, int, bool, bool, bool, int, const Sched&); \
   template hipError_t launch_steps_profiled<N>(RunView&, int, double*);                               \
   template void launch_prologue<N>(RunView&);                                                         \
   template void launch_io_row_forward<N>(RunView&, const IoRowFwd&, int);                             \

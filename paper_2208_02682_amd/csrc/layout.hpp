@@ -48,16 +48,22 @@ enum RowSpec : int {
   RS_ZV = 0, RS_ZU, RS_K, RS_HU, RS_HV,         // zeta v, zeta u, (u^2+v^2)/2, eta u, eta v
   RS_XIX, RS_XIY, RS_GBH, RS_GBZ, RS_GTH, RS_GTZ, RS_PX, RS_PY,
   RS_GMX, RS_GMY,
-  NRS = 15
+  RS_F0, RS_F1,      // the two averaged fields themselves (Eulerian means of other fields than h, zeta)
+  NRS = 17
 };
 
 // column-kernel work groups (one prognostic field each; E_h, E_zeta ride with h)
-// (the momentum groups come last and are launched only when requested)
+// (the momentum groups come next and are launched only when requested, then the
+// Eulerian-mean groups of averaged fields other than (h, zeta))
 enum ColGroup : int {
   CG_U = 0, CG_V, CG_H, CG_XIX, CG_XIY, CG_GBH, CG_GBZ, CG_GTH, CG_GTZ, CG_PX, CG_PY,
   NCG = 11,
-  CG_GMX = 11, CG_GMY, NCG_MOM = 13
+  CG_GMX = 11, CG_GMY, NCG_MOM = 13,
+  CG_EF0 = 13, CG_EF1
 };
+
+// the fields the two averaging slots can hold (f_0, f_1; the default is (eta, zeta))
+enum FieldSel : int { FS_ETA = 0, FS_ZETA, FS_U, FS_V, FS_Q /* (f + zeta) / h */ };
 
 // row-kernel tasks of the right-hand-side pass (the momentum rows, when
 // requested, are a kernel of their own with one task per component)
@@ -82,9 +88,26 @@ struct Dims {
   __host__ __device__ size_t rowfield_elems() const { return (size_t)N * NKXP; }
 };
 
-// physics constants of one run
+// physics constants of one run, and what its launches compute
 struct Phys {
   double f, g, H, dt, nu8;
+  int fs0, fs1;  // FieldSel of averaging slots 0 and 1
+  int gen;       // Eulerian means from transforms of the averaged fields (any pair but (eta, zeta))
+  int mom;       // the momentum 1-form groups are launched
+  int kin;       // u, v, h prescribed: a linear plane wave plus a uniform flow (no dynamics)
+  double kx, ky, A, omega, phase, U0, V0;  // kinematic: h' = A cos(kx x + ky y - omega t + phase)
 };
+
+// column groups launched for a run: blockIdx.y -> ColGroup
+__host__ __device__ inline int col_groups(const Phys& ph) { return NCG + (ph.mom ? 2 : 0) + (ph.gen ? 2 : 0); }
+__host__ __device__ inline int col_group_of(const Phys& ph, int y) {
+  if (y < NCG) return y;
+  y -= NCG;
+  if (ph.mom) {
+    if (y < 2) return CG_GMX + y;
+    y -= 2;
+  }
+  return CG_EF0 + y;
+}
 
 }  // namespace lm

@@ -32,8 +32,10 @@ struct Layout {
 };
 
 // mom: also room for the strategy-2 mean of the momentum 1-form (its state,
-// intermediates, row spectra and two output planes come last)
-inline Layout make_layout(const Dims& d, bool fp32, bool mom) {
+// intermediates, row spectra and two output planes come last); gen: also the
+// row spectra of the two averaged fields (Eulerian means of fields other than
+// h and zeta)
+inline Layout make_layout(const Dims& d, bool fp32, bool mom, bool gen) {
   const size_t cT = fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
   const size_t cD = sizeof(cplx<double>);
   const size_t sp = d.spec_elems(), rf = d.rowfield_elems(), nn = (size_t)d.N * d.N;
@@ -44,7 +46,8 @@ inline Layout make_layout(const Dims& d, bool fp32, bool mom) {
     o += slab_up(bytes);
     return at;
   };
-  const int nsf = mom ? NSF_R : SF_GMX, nic = mom ? NIC : IC_GMX, nrs = mom ? NRS : RS_GMX;
+  const int nsf = mom ? NSF_R : SF_GMX, nic = mom ? NIC : IC_GMX;
+  const int nrs = gen ? NRS : (mom ? RS_GMY + 1 : RS_GMX);
   L.Yr = take(nsf * sp * cT);
   // float state is carried in two words (leading in Yr, trailing here)
   L.Yl = take(fp32 ? nsf * sp * cT : 0);
@@ -73,6 +76,15 @@ inline Layout make_layout(const Dims& d, bool fp32, bool mom) {
 struct Sched {
   int tile = 0;   // -1: half the default column tile width, 0: default, +1: twice
   int remap = 1;  // 1: XCD-aware block order, 0: hardware order
+};
+
+// Waits for a stream when it leaves scope, on every path out of a call: no
+// copy or kernel the call enqueued can still touch a caller's buffer, a stack
+// variable of the call, or memory released after the call returned.  (The
+// wait's own status is not reported: an error path already has one.)
+struct StreamDrain {
+  hipStream_t s;
+  ~StreamDrain() { (void)hipStreamSynchronize(s); }
 };
 
 struct RunView {
@@ -113,6 +125,7 @@ RunDesc<T> run_desc(RunView& r, const long long* counter) {
   D.Ys0 = (cplx<T>*)r.at(r.L.Ys0);
   D.Ys1 = (cplx<T>*)r.at(r.L.Ys1);
   D.counter = counter;
+  D.n_tau = r.n_tau;
   return D;
 }
 

@@ -32,6 +32,7 @@ struct RunDesc {
   cplx<T>* Ys0;              // stage values of u, v, h (ping-pong buffers)
   cplx<T>* Ys1;
   const long long* counter;  // RK4 steps since the interval start
+  long long n_tau;           // steps from the state's time origin to the interval start
 };
 
 }  // namespace lm

@@ -263,8 +263,21 @@ __device__ __forceinline__ P4<T> gather4(const P4<T>* __restrict__ F, int x, int
 // --------------------------------------------------------------------------
 // rows_dyn
 // --------------------------------------------------------------------------
+// value of an averaging slot's field at a point (FieldSel)
+template <typename T>
+__device__ __forceinline__ T field_value(int fs, const cplx<T>& uv, const cplx<T>& hz, const Phys& ph) {
+  switch (fs) {
+    case FS_ETA: return hz.x;
+    case FS_ZETA: return hz.y;
+    case FS_U: return uv.x;
+    case FS_V: return uv.y;
+    default: return (T(ph.f) + hz.y) / (T(ph.H) + hz.x);  // potential vorticity (f + zeta) / h
+  }
+}
+
 template <typename T, int N>
-__device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& d, int rowblock, cplx<T>* lds) {
+__device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& d, const Phys& ph, int rowblock,
+                                              cplx<T>* lds) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
   const int grp = row_group<NT>(), t = threadIdx.x % NT;
@@ -299,12 +312,25 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
   }
   inverse_row<T, N>(hz, buf, t, P.tw);
 
+  // u, v and the two averaged fields, interleaved for the gathers
   P4<T>* out = P.uvhz + (size_t)y * N;
-#pragma unroll
-  for (int e = 0; e < E; ++e) out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, hz[e].x, hz[e].y};
-
   cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
   cplx<T> z[E];
+  if (ph.fs0 == FS_ETA && ph.fs1 == FS_ZETA) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, hz[e].x, hz[e].y};
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      z[e] = {field_value<T>(ph.fs0, uv[e], hz[e], ph), field_value<T>(ph.fs1, uv[e], hz[e], ph)};
+      out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, z[e].x, z[e].y};
+    }
+    // their spectra, for the Eulerian means
+    if (ph.gen) forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_F0 * rf, RSr + RS_F1 * rf);
+  }
+  if (ph.kin) return;  // prescribed flow: no dynamics
+
+
 #pragma unroll
   for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
   forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
@@ -318,11 +344,11 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d, int remap) {
+__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d, Phys ph, int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, unused, z;
   xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
-  rows_dyn_body<T, N>(P, d, rowblock, lds);
+  rows_dyn_body<T, N>(P, d, ph, rowblock, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -717,26 +743,72 @@ __device__ __forceinline__ void column_inverse(const ColCtx<T, N, C>& cx, const 
   tile_store<T, N, C>(cx, dst, d);
 }
 
+// Fourier coefficient (the stored kx >= 0 half, 1/N^2-normalised) of u, v or h
+// (G = CG_U, CG_V, CG_H) of the prescribed flow at time t: a linear Poincare
+// plane wave h' = A cos(theta), theta = k.x - omega t + phase, with the linear
+// shallow-water polarisation of section 4.2.1, eq. (4.8), in any direction,
+//   u' = A (omega kx cos(theta) - f ky sin(theta)) / (H |k|^2),
+//   v' = A (omega ky cos(theta) + f kx sin(theta)) / (H |k|^2),
+// plus the uniform flow (U0, V0), and the depth H at k = 0.  With
+// cos(theta) = (e^{i theta} + e^{-i theta}) / 2 the +k mode's coefficient is
+// (A / 2) C e^{i (phase - omega t)}, C = 1, (omega kx + i f ky) / (H |k|^2) or
+// (omega ky - i f kx) / (H |k|^2); a stored entry at -k holds its conjugate.
+template <int G>
+__device__ cplx<double> kin_coef(int kx, int ky, double t, const Phys& ph) {
+  cplx<double> c = {0.0, 0.0};
+  if (kx == 0 && ky == 0) c.x = (G == CG_U) ? ph.U0 : (G == CG_V) ? ph.V0 : ph.H;
+  const int wx = int(ph.kx), wy = int(ph.ky);
+  const bool plus = (kx == wx && ky == wy), minus = (kx == -wx && ky == -wy);
+  if ((wx == 0 && wy == 0) || !(plus || minus)) return c;
+  const double k2 = ph.kx * ph.kx + ph.ky * ph.ky;
+  double cr = 1.0, ci = 0.0;
+  if (G == CG_U) {
+    cr = ph.omega * ph.kx / (ph.H * k2);
+    ci = ph.f * ph.ky / (ph.H * k2);
+  } else if (G == CG_V) {
+    cr = ph.omega * ph.ky / (ph.H * k2);
+    ci = -ph.f * ph.kx / (ph.H * k2);
+  }
+  double sn, cs;
+  sincos(ph.phase - ph.omega * t, &sn, &cs);
+  const double a = 0.5 * ph.A;
+  cplx<double> m = {a * (cr * cs - ci * sn), a * (cr * sn + ci * cs)};
+  if (minus) m.y = -m.y;
+  c.x += m.x;
+  c.y += m.y;
+  return c;
+}
+
+// stage >= 0: the RK4 stage; stage < 0: the prologue (the current state's
+// column-pass outputs only).  t_next: time of the stage input this launch
+// prepares (the prescribed flow of a kinematic run is evaluated there).
 template <typename T, int N, int C, int G>
 __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const StepPtrs<T>& P, const Dims& d,
-                                             const Phys& ph, int stage, const cplx<T>* __restrict__ Ys_in,
-                                             cplx<T>* __restrict__ Ys_out) {
+                                             const Phys& ph, int stage, double t_next,
+                                             const cplx<T>* __restrict__ Ys_in, cplx<T>* __restrict__ Ys_out) {
   constexpr int E = fft_E<N>(), NT = N / E;
   constexpr bool DBL = (G == CG_XIX || G == CG_XIY || G == CG_PX || G == CG_PY);
+  constexpr bool DYN = (G == CG_U || G == CG_V || G == CG_H);
+  constexpr bool EUL = (G == CG_EF0 || G == CG_EF1);  // Eulerian accumulators of the averaged fields
   using TS = typename std::conditional<DBL, double, T>::type;
   const size_t sp = d.spec_elems();
   const size_t rf = d.rowfield_elems();
   constexpr int K = kcut<N>();
+  if constexpr (EUL) {
+    if (stage < 0) return;  // not an input of the rows passes
+  }
 
   // right-hand-side inputs of this group
-  constexpr int NF = (G == CG_U || G == CG_V || G == CG_H) ? 2 : 1;
+  constexpr int NF = DYN ? 2 : 1;
   constexpr int F0 = (G == CG_U) ? RS_ZV : (G == CG_V) ? RS_ZU : (G == CG_H) ? RS_HU
                    : (G == CG_XIX) ? RS_XIX : (G == CG_XIY) ? RS_XIY : (G == CG_GBH) ? RS_GBH
                    : (G == CG_GBZ) ? RS_GBZ : (G == CG_GTH) ? RS_GTH : (G == CG_GTZ) ? RS_GTZ
-                   : (G == CG_PX) ? RS_PX : (G == CG_PY) ? RS_PY : (G == CG_GMX) ? RS_GMX : RS_GMY;
+                   : (G == CG_PX) ? RS_PX : (G == CG_PY) ? RS_PY : (G == CG_GMX) ? RS_GMX
+                   : (G == CG_GMY) ? RS_GMY : (G == CG_EF0) ? RS_F0 : RS_F1;
   constexpr int F1 = (G == CG_U || G == CG_V) ? RS_K : RS_HV;
   cplx<T> r0[E], r1[E];
-  if (stage >= 0) {
+  // a kinematic run has no dynamics right-hand sides
+  if (stage >= 0 && !(DYN && ph.kin)) {
     column_forward<T, N, C>(cx, P.RS + F0 * rf, d, P.tw, r0);
     if constexpr (NF == 2) column_forward<T, N, C>(cx, P.RS + F1 * rf, d, P.tw, r1);
   }
@@ -752,13 +824,13 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
   } else {
     constexpr int sr = (G == CG_U) ? SF_U : (G == CG_V) ? SF_V : (G == CG_H) ? SF_H : (G == CG_GBH) ? SF_GBH
                      : (G == CG_GBZ) ? SF_GBZ : (G == CG_GTH) ? SF_GTH : (G == CG_GTZ) ? SF_GTZ
-                     : (G == CG_GMX) ? SF_GMX : SF_GMY;
+                     : (G == CG_GMX) ? SF_GMX : (G == CG_GMY) ? SF_GMY : (G == CG_EF0) ? SF_EH : SF_EZ;
     Y = reinterpret_cast<cplx<TS>*>(P.Yr) + sr * sp;
     if constexpr (std::is_same<TS, float>::value) YL = reinterpret_cast<cplx<TS>*>(P.Yl) + sr * sp;
     A = reinterpret_cast<cplx<TS>*>(P.Ar) + sr * sp;
   }
   const size_t col = (size_t)cx.kx * d.NKY;
-  const T fT = T(ph.f), gT = T(ph.g);
+  const T fT = T(ph.f), gT = T(ph.g), HT = T(ph.H);
 
   cplx<TS> S[E];
 #pragma unroll
@@ -772,12 +844,34 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     S[r] = {TS(0), TS(0)};
     if (!(in && cx.valid)) continue;
     const size_t j = col + (size_t)(ky + K);
+    const T kxT = T(cx.kx), kyT = T(ky);
+    if constexpr (G == CG_H) {
+      // Eulerian accumulators of (eta, zeta) from the stage values: dE_eta/dt = eta
+      // (h less H at k = 0), dE_zeta/dt = i kx v - i ky u (other averaged fields:
+      // groups CG_EF0 / CG_EF1)
+      if (stage >= 0 && !ph.gen) {
+        const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
+        cplx<T> eta = h;
+        if (cx.kx == 0 && ky == 0) eta.x -= HT;
+        rk4<T>(stage, P.Yr + SF_EH * sp + j, P.Yl + SF_EH * sp + j, P.Ar + SF_EH * sp + j, eta, ph.dt);
+        const cplx<T> zeta = {-kxT * v.y + kyT * u.y, kxT * v.x - kyT * u.x};
+        rk4<T>(stage, P.Yr + SF_EZ * sp + j, P.Yl + SF_EZ * sp + j, P.Ar + SF_EZ * sp + j, zeta, ph.dt);
+      }
+    }
+    if constexpr (DYN) {
+      if (ph.kin) {
+        // prescribed flow: the next stage input is the flow at t_next
+        const cplx<double> c = kin_coef<G>(cx.kx, ky, t_next, ph);
+        S[r] = {TS(c.x), TS(c.y)};
+        Ys_out[(G - CG_U) * sp + j] = S[r];
+        continue;
+      }
+    }
     if (stage < 0) {
       S[r] = Y[j];
-      if constexpr (G == CG_U || G == CG_V || G == CG_H) Ys_out[(G - CG_U) * sp + j] = S[r];
+      if constexpr (DYN) Ys_out[(G - CG_U) * sp + j] = S[r];
       continue;
     }
-    const T kxT = T(cx.kx), kyT = T(ky);
     const double k2 = double(cx.kx) * cx.kx + double(ky) * ky;
     const T hv = T(ph.nu8 * (k2 * k2) * (k2 * k2));
     cplx<T> R;
@@ -794,25 +888,15 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     } else if constexpr (G == CG_H) {
       // -i kx (H u + F(eta u)) - i ky (H v + F(eta v)) - nu8 |k|^8 h
       const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
-      const T HT = T(ph.H);
       const cplx<T> fx = {HT * u.x + r0[r].x, HT * u.y + r0[r].y};
       const cplx<T> fy = {HT * v.x + r1[r].x, HT * v.y + r1[r].y};
       R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
-      // Eulerian accumulators: dE_eta/dt = eta (h less H at k = 0), dE_zeta/dt = i kx v - i ky u
-      cplx<T>* Yr = P.Yr;
-      cplx<T>* Yl = P.Yl;
-      cplx<T>* Ar = P.Ar;
-      cplx<T> eta = h;
-      if (cx.kx == 0 && ky == 0) eta.x -= HT;
-      rk4<T>(stage, Yr + SF_EH * sp + j, Yl + SF_EH * sp + j, Ar + SF_EH * sp + j, eta, ph.dt);
-      const cplx<T> zeta = {-kxT * v.y + kyT * u.y, kxT * v.x - kyT * u.x};
-      rk4<T>(stage, Yr + SF_EZ * sp + j, Yl + SF_EZ * sp + j, Ar + SF_EZ * sp + j, zeta, ph.dt);
     } else {
       R = r0[r];
     }
     const cplx<TS> Rk = {TS(R.x), TS(R.y)};
     S[r] = rk4<TS>(stage, Y + j, YL + j, A + j, Rk, ph.dt);
-    if constexpr (G == CG_U || G == CG_V || G == CG_H) Ys_out[(G - CG_U) * sp + j] = S[r];
+    if constexpr (DYN) Ys_out[(G - CG_U) * sp + j] = S[r];
   }
 
   // inverse column transforms of the next stage input
@@ -825,7 +909,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     // the rows passes work with eta = h - H: drop H from the mean (k = 0, lane 0)
     if (cx.kx == 0 && cx.t == 0) S[0].x -= TS(ph.H);
     column_inverse<T, N, C, TS, false>(cx, S, P.IC + IC_H * rf, d, P.tw);
-  } else {
+  } else if constexpr (!EUL) {
     constexpr int o = (G == CG_XIX) ? IC_XIX : (G == CG_XIY) ? IC_XIY : (G == CG_GBH) ? IC_GBH
                     : (G == CG_GBZ) ? IC_GBZ : (G == CG_GTH) ? IC_GTH : (G == CG_GTZ) ? IC_GTZ
                     : (G == CG_PX) ? IC_PX : (G == CG_PY) ? IC_PY : (G == CG_GMX) ? IC_GMX : IC_GMY;
@@ -837,8 +921,8 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
 // stage >= 0: RK4 stage; stage < 0: only transform the current state (prologue)
 template <typename T, int N, int C>
 __device__ __forceinline__ void columns_body(const StepPtrs<T>& P, const Dims& d, const Phys& ph, int stage,
-                                             const cplx<T>* Ys_in, cplx<T>* Ys_out, int tile, int group,
-                                             cplx<T>* lds) {
+                                             double t_next, const cplx<T>* Ys_in, cplx<T>* Ys_out, int tile,
+                                             int slot, cplx<T>* lds) {
   constexpr int E = fft_E<N>(), NT = N / E, LC = col_buf(N);
   ColCtx<T, N, C> cx;
   cx.lds = lds;
@@ -848,22 +932,16 @@ __device__ __forceinline__ void columns_body(const StepPtrs<T>& P, const Dims& d
   cx.kx0 = tile * C;
   cx.kx = cx.kx0 + cx.c;
   cx.valid = cx.kx <= kcut<N>();
-  switch (group) {
-    case CG_U: column_group<T, N, C, CG_U>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_V: column_group<T, N, C, CG_V>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_H: column_group<T, N, C, CG_H>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_XIX: column_group<T, N, C, CG_XIX>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_XIY: column_group<T, N, C, CG_XIY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_GBH: column_group<T, N, C, CG_GBH>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_GBZ: column_group<T, N, C, CG_GBZ>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_GTH: column_group<T, N, C, CG_GTH>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_GTZ: column_group<T, N, C, CG_GTZ>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_PX: column_group<T, N, C, CG_PX>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_PY: column_group<T, N, C, CG_PY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_GMX: column_group<T, N, C, CG_GMX>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
-    case CG_GMY: column_group<T, N, C, CG_GMY>(cx, P, d, ph, stage, Ys_in, Ys_out); break;
+  (void)E;
+#define LM_CG(g) \
+  case g: column_group<T, N, C, g>(cx, P, d, ph, stage, t_next, Ys_in, Ys_out); break
+  switch (col_group_of(ph, slot)) {
+    LM_CG(CG_U); LM_CG(CG_V); LM_CG(CG_H); LM_CG(CG_XIX); LM_CG(CG_XIY); LM_CG(CG_GBH); LM_CG(CG_GBZ);
+    LM_CG(CG_GTH); LM_CG(CG_GTZ); LM_CG(CG_PX); LM_CG(CG_PY); LM_CG(CG_GMX); LM_CG(CG_GMY);
+    LM_CG(CG_EF0); LM_CG(CG_EF1);
     default: break;
   }
+#undef LM_CG
 }
 
 // float32: ask for 4 resident waves per SIMD (at most 128 VGPRs) where the kernel
@@ -877,11 +955,12 @@ __host__ __device__ constexpr int col_waves() {
 // W: column tile width (col_tile<N, W>)
 template <typename T, int N, int W>
 __global__ void __launch_bounds__((col_threads<N, W>()), (col_waves<T, N, false>()))
-    k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, const cplx<T>* Ys_in, cplx<T>* Ys_out, int remap) {
+    k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, double t_next, const cplx<T>* Ys_in, cplx<T>* Ys_out,
+              int remap) {
   __shared__ cplx<T> lds[col_tile<N, W>() * col_buf(N)];
   int tile, group, z;
   xcd_split(gridDim.x, gridDim.y, tile, group, z, remap);  // grid = (column tiles, field groups)
-  columns_body<T, N, col_tile<N, W>()>(P, d, ph, stage, Ys_in, Ys_out, tile, group, lds);
+  columns_body<T, N, col_tile<N, W>()>(P, d, ph, stage, t_next, Ys_in, Ys_out, tile, group, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -893,7 +972,7 @@ __global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn_b(const RunDesc<T>*
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
   int rowblock, unused, z;
   xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
-  rows_dyn_body<T, N>(runs[z].P, Dims::make(N), rowblock, lds);
+  rows_dyn_body<T, N>(runs[z].P, Dims::make(N), runs[z].ph, rowblock, lds);
 }
 
 template <typename T, int N, bool CUB>
@@ -930,7 +1009,10 @@ __global__ void __launch_bounds__((col_threads<N, W>()), (col_waves<T, N, true>(
   const RunDesc<T>& R = runs[z];
   const cplx<T>* Ys_in = (stage & 1) ? R.Ys1 : R.Ys0;
   cplx<T>* Ys_out = (stage & 1) ? R.Ys0 : R.Ys1;
-  columns_body<T, N, col_tile<N, W>()>(R.P, Dims::make(N), R.ph, stage, Ys_in, Ys_out, tile, group, lds);
+  // time of the next stage input, from integers (as the single-run path)
+  const double cn = (stage <= 1) ? 0.5 : 1.0;
+  const double t_next = (double(R.n_tau + *R.counter) + cn) * R.ph.dt;
+  columns_body<T, N, col_tile<N, W>()>(R.P, Dims::make(N), R.ph, stage, t_next, Ys_in, Ys_out, tile, group, lds);
 }
 
 }  // namespace lm

@@ -24,7 +24,9 @@ STATUS = {0: "LM_OK", -1: "LM_E_ARG", -2: "LM_E_STATE", -3: "LM_E_OOM", -4: "LM_
 LM_FP64, LM_FP32_MIXED = 0, 1
 (LM_K_S2_MEAN, LM_K_S2_XI_X, LM_K_S2_XI_Y, LM_K_S1_MEAN, LM_K_S1_ETA_X, LM_K_S1_ETA_Y, LM_K_EULER_MEAN,
  LM_K_S1_REMAP_MEAN, LM_K_S1_REMAP_XI_X, LM_K_S1_REMAP_XI_Y, LM_K_S2_MOM_X, LM_K_S2_MOM_Y) = range(12)
-LM_F_H, LM_F_ZETA, LM_F_MOMENTUM = 1, 2, 4
+LM_F_H, LM_F_ZETA, LM_F_MOMENTUM, LM_F_U, LM_F_V, LM_F_Q = 1, 2, 4, 8, 16, 32
+FIELD_BITS = {"h": LM_F_H, "zeta": LM_F_ZETA, "u": LM_F_U, "v": LM_F_V, "q": LM_F_Q}
+LM_DYNAMIC, LM_KINEMATIC_PLANEWAVE = 0, 1
 LM_FIELD_H, LM_FIELD_ZETA = 0, 1
 PEEK = {"u": 0, "v": 1, "h": 2, "gbar:h": 3, "gbar:zeta": 4, "gtil:h": 5, "gtil:zeta": 6,
         "E:h": 7, "E:zeta": 8, "xi_x": 9, "xi_y": 10, "P_x": 11, "P_y": 12}
@@ -56,7 +58,7 @@ class Config(ctypes.Structure):
                 ("f", ctypes.c_double), ("g", ctypes.c_double), ("H", ctypes.c_double),
                 ("dt", ctypes.c_double), ("nu8", ctypes.c_double),
                 ("avg_fields", ctypes.c_uint32), ("strategies", ctypes.c_uint32),
-                ("interp", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("interp", ctypes.c_int32), ("mode", ctypes.c_int32), ("kin", ctypes.c_double * 8)]
 
 
 class E2DConfig(ctypes.Structure):
@@ -77,6 +79,12 @@ E2D_OUTPUTS = {"zeta": 0, "PS_mean": 1, "PS_eta_x": 2, "PS_eta_y": 3, "SL_mean":
 _lib: Optional[ctypes.CDLL] = None
 
 
+# LAGMEAN_HIP_RUNTIME=own: load the library without PyTorch, so that it binds
+# the HIP runtime it was built with (for processes that need no torch, such as
+# the serving loop on host arrays).  Default: PyTorch's runtime (see below).
+OWN_RUNTIME_ENV = "LAGMEAN_HIP_RUNTIME"
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
@@ -86,11 +94,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     # One HIP runtime per process.  PyTorch ships its own libamdhip64 (same
     # soname); loaded first, it is the runtime the library binds to.  Loaded
     # after the library, torch would bring a second runtime that does not see
-    # the GPU.  So torch, when present, is loaded before the library.
-    try:
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    # the GPU.  So torch, when present, is loaded before the library, unless the
+    # caller asked for the library's own runtime (and then must not use torch's
+    # GPU functions in this process).
+    if os.environ.get(OWN_RUNTIME_ENV, "") != "own":
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     D = ctypes.POINTER(ctypes.c_double)
@@ -108,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_peek": [P, ctypes.c_int32, P, ctypes.c_int],
         "lm_counters": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "lm_destroy": [P],
+        "lm_hip_versions": [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
         "lm_batch_create": [P, ctypes.POINTER(P)],
         "lm_batch_add": [P, P, ctypes.c_int32],
         "lm_batch_remove": [P, P],
@@ -154,11 +166,31 @@ LM_INTERP = {"bilinear": 0, "cubic": 1}
 
 
 def make_config(n: int, *, precision: str = "fp64", f: float = 1.0, g: float = 1.0, H: float = 1.0,
-                dt: float, nu8: float = 0.0, interp: str = "bilinear", momentum: bool = False) -> Config:
+                dt: float, nu8: float = 0.0, interp: str = "bilinear", momentum: bool = False,
+                fields: Tuple[str, str] = ("h", "zeta"), kinematic: Optional[dict] = None) -> Config:
+    """fields: the two averaged scalar fields (names of FIELD_BITS; output slot 0
+    is the one with the lower bit).  kinematic: a prescribed flow instead of
+    the dynamics, {"kx", "ky", "A", "omega" (0: dispersion), "phase", "U0", "V0"}."""
     prec = {"fp64": LM_FP64, "fp32": LM_FP32_MIXED}[precision]
-    fields = (LM_F_H | LM_F_ZETA | LM_F_MOMENTUM) if momentum else 0
-    return Config(n=n, precision=prec, f=f, g=g, H=H, dt=dt, nu8=nu8, avg_fields=fields, strategies=0,
-                  interp=LM_INTERP[interp], mode=0)
+    if len(fields) != 2 or len(set(fields)) != 2:
+        raise ValueError("two distinct averaged fields")
+    mask = FIELD_BITS[fields[0]] | FIELD_BITS[fields[1]]
+    if momentum:
+        mask |= LM_F_MOMENTUM
+    cfg = Config(n=n, precision=prec, f=f, g=g, H=H, dt=dt, nu8=nu8, avg_fields=mask, strategies=0,
+                 interp=LM_INTERP[interp], mode=LM_DYNAMIC)
+    if kinematic is not None:
+        cfg.mode = LM_KINEMATIC_PLANEWAVE
+        for i, key in enumerate(("kx", "ky", "A", "omega", "phase", "U0", "V0")):
+            cfg.kin[i] = float(kinematic.get(key, 0.0))
+    return cfg
+
+
+def field_slots(cfg: Config) -> Tuple[str, str]:
+    """Names of the fields in output slots 0 and 1 of a configuration."""
+    mask = int(cfg.avg_fields) & ~LM_F_MOMENTUM or (LM_F_H | LM_F_ZETA)
+    names = [n for n, b in sorted(FIELD_BITS.items(), key=lambda kv: kv[1]) if mask & b]
+    return names[0], names[1]
 
 
 PRECISIONS = {"fp64": LM_FP64, "fp32": LM_FP32_MIXED}
@@ -216,6 +248,24 @@ def load_schedules(path: str, arch: Optional[str] = None) -> int:
         set_schedule(int(e["n"]), e["precision"], int(e["col_tile"]), int(e["xcd_order"]),
                      batched=e.get("context", "single") == "batched")
     return len(doc["entries"])
+
+
+def hip_runtime() -> Dict[str, object]:
+    """HIP versions the library was built with and runs on (lm_hip_versions),
+    and the file of the HIP runtime the process has mapped."""
+    lib = load_library()
+    built, runtime = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib.lm_hip_versions(ctypes.byref(built), ctypes.byref(runtime)))
+    files = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    files.add(line.split()[-1])
+    except OSError:
+        pass
+    return {"built": int(built.value), "runtime": int(runtime.value), "runtime_files": sorted(files),
+            "same": int(built.value) // 100000 == int(runtime.value) // 100000}
 
 
 def footprint(cfg: Config) -> int:
@@ -310,7 +360,22 @@ class Run:
         return out
 
     def outputs(self) -> Dict[str, np.ndarray]:
+        """The interval's outputs, named as the oracle's (the default fields h and
+        zeta); runs averaging other fields use field_outputs."""
         return {name: self.read_mean(fk[0], fk[1]) for name, fk in OUTPUTS.items()}
+
+    def field_outputs(self) -> Dict[str, np.ndarray]:
+        """The interval's outputs named by the run's averaged fields, as the
+        oracle names them (e.g. "S2_mean:u", "S1_mean:q", "E_mean:v", "S2_xi_x")."""
+        slots = field_slots(self.cfg)
+        out = {}
+        for name, (fld, kind) in OUTPUTS.items():
+            if ":" in name:
+                base = name.split(":")[0]
+                out[f"{base}:{slots[fld]}"] = self.read_mean(fld, kind)
+            else:
+                out[name] = self.read_mean(fld, kind)
+        return out
 
     def remap_s1(self, max_extent: int = 64) -> float:
         """Strategy 1 at Lagrangian-mean positions (lm_remap_s1); returns the
