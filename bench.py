@@ -378,16 +378,70 @@ def _serve_once(reqs, states, rate, window, a, t_limit):
             "capacity_pt_steps_per_s": capacity, "rho": offered / capacity, **stats}
 
 
-def bench_serve(a) -> dict:
+def _fp64_sequential(reqs, a) -> dict:
+    """The same requests served one after another as plain float64 single runs:
+    the first --fp64-sample requests of every grid size are run and timed (state
+    handed over -> all means on the host), which gives each size's float64
+    service rate; the first-come-first-served latency of a sequential float64
+    server over the whole arrival sequence then follows from those measured
+    rates (each request's service time = its grid-point steps / its size's rate)."""
     import numpy as np
-    import torch
+    from paper_2208_02682_amd import Run
+    per_n = {}
+    for r in reqs:
+        per_n.setdefault(r.run.N, [])
+        if len(per_n[r.run.N]) < a.fp64_sample:
+            per_n[r.run.N].append(r)
+    rate, measured = {}, 0
+    for N, sample in sorted(per_n.items()):
+        states = generate_states([r.run for r in sample])
+        with Run(_cfg(sample[0].run, "fp64")) as run:
+            run.set_state(*states[0])  # warm-up
+            run.begin_interval()
+            run.step(2)
+            run.end_interval()
+            work, t_all = 0, 0.0
+            for r, st in zip(sample, states):
+                t0 = time.perf_counter()
+                run.set_state(*st)
+                run.begin_interval()
+                run.step(r.run.steps_per_interval)
+                run.end_interval()
+                out = run.outputs()
+                t_all += time.perf_counter() - t0
+                work += r.run.N * r.run.N * r.run.steps_per_interval
+                assert all(np.isfinite(v).all() for v in out.values())
+        rate[N] = work / t_all
+        measured += len(sample)
+        print(f"serve: float64 sequential, N={N}: {len(sample)} requests at {rate[N]:.3e} pt-steps/s",
+              file=sys.stderr, flush=True)
+    free, lat = 0.0, []
+    for r in reqs:
+        svc = r.run.N * r.run.N * r.run.steps_per_interval / rate[r.run.N]
+        start = max(free, r.arrival)
+        free = start + svc
+        lat.append(free - r.arrival)
+    lat = np.array(lat)
+    total = sum(r.run.N * r.run.N * r.run.steps_per_interval for r in reqs)
+    busy = sum(r.run.N * r.run.N * r.run.steps_per_interval / rate[r.run.N] for r in reqs)
+    return {"measured_requests": measured, "sample_per_size": a.fp64_sample,
+            "pt_steps_per_s_by_N": {str(N): v for N, v in sorted(rate.items())},
+            "capacity_pt_steps_per_s": total / busy,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "note": "latencies of a first-come-first-served sequential float64 server over the same arrivals, "
+                    "from the service rates measured on the sampled requests"}
+
+
+def bench_serve(a) -> dict:
+    """Runs without torch (host arrays, the null stream): the library binds its own HIP runtime."""
+    import numpy as np
+    from paper_2208_02682_amd import hip_runtime
     from synth.workloads import serving_requests
 
     reqs = serving_requests(rate=a.rate, duration=a.window, seed=7)
     sizes = sorted({r.run.N for r in reqs})
     states = generate_states([r.run for r in reqs])
     print(f"serve: {len(reqs)} request states generated", file=sys.stderr, flush=True)
-    torch.cuda.set_device(0)
     first = {}
     for r, st in zip(reqs, states):
         first.setdefault(r.run.N, (r.run, st))
@@ -404,7 +458,9 @@ def bench_serve(a) -> dict:
                       "mean_grid_point_steps_per_request": mean_work, "hbm_budget_gib": a.hbm_budget_gib,
                       "max_resident_points": a.max_resident_points, "tick_steps": a.tick_steps,
                       "schedule_source": source},
+           "hip": hip_runtime(), "torch_loaded": "torch" in sys.modules,
            "offered": main}
+    rec["fp64_sequential"] = _fp64_sequential(reqs, a)
     if a.sustainable_window > 0 and np.isfinite(main["capacity_pt_steps_per_s"]):
         rate = 0.7 * main["capacity_pt_steps_per_s"] / mean_work
         reqs2 = serving_requests(rate=rate, duration=a.sustainable_window, seed=7)
@@ -559,6 +615,8 @@ def main(argv=None) -> int:
     ap.add_argument("--drain-limit", type=float, default=300.0,
                     help="serve: seconds after the last arrival before unfinished requests are counted as such")
     ap.add_argument("--hbm-budget-gib", type=float, default=64.0)
+    ap.add_argument("--fp64-sample", type=int, default=6,
+                    help="serve: requests per grid size timed as plain float64 single runs")
     ap.add_argument("--max-resident-points", type=int, default=8 * 1024 * 1024)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates "
@@ -570,12 +628,12 @@ def main(argv=None) -> int:
         return 2
 
     if a.mode == "serve":
-        # the last run of this mode (schedule cache applied, 577 requests) ended in a
-        # segmentation fault of the host process after about 200 requests; until its
-        # cause is found the mode stays disabled (the serving loop's tests still run)
-        print("bench.py --mode serve is disabled: its last run ended in a host segmentation fault "
-              "whose cause has not been found", file=sys.stderr)
-        return 2
+        # the serving loop needs no torch: the library binds the HIP runtime it
+        # was built with (an earlier run of this mode, with torch's older runtime
+        # bound under the library, ended in a host segmentation fault)
+        os.environ["LAGMEAN_HIP_RUNTIME"] = "own"
+        import faulthandler
+        faulthandler.enable()
     if a.mode in ("batch", "serve", "euler", "tune", "latency"):
         rec = {"batch": bench_batch, "serve": bench_serve, "euler": bench_euler, "tune": bench_tune,
                "latency": bench_latency}[a.mode](a)

@@ -1,0 +1,77 @@
+"""The library in a process without PyTorch, bound to the HIP runtime it was built with.
+
+PyTorch ships its own HIP runtime (same soname); a process that imports torch
+first makes the library bind to that one, whose version differs from the
+headers the library was compiled with.  Processes that need no torch (the
+serving loop on host arrays) can load the library alone (LAGMEAN_HIP_RUNTIME=own).
+This test runs such a process: it checks which runtime was bound, and that a
+single run and a batched run give the oracle's results at 1e-12.
+"""
+
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import OUTPUT_KEYS, compare_value, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CHILD = r"""
+import json, sys
+import numpy as np
+sys.path.insert(0, ROOT)
+import paper_2208_02682_amd as L
+from synth import workload
+assert "torch" not in sys.modules
+w = workload("sw64_fp64")
+u, v, h = w.initial_state()
+cfg = L.make_config(w.N, precision="fp64", dt=w.dt, nu8=w.nu8)
+single = L.Run(cfg)
+single.set_state(u, v, h)
+single.begin_interval()
+single.step(40)
+single.end_interval()
+a = single.outputs()
+batched = L.Run(cfg)
+batched.set_state(u, v, h)
+batched.begin_interval()
+with L.Batch() as b:
+    b.add(batched, 40)
+    while b.step(16):
+        pass
+    b.remove(batched)
+batched.end_interval()
+c = batched.outputs()
+np.savez(OUT, **{"single_" + k.replace(":", "_"): x for k, x in a.items()},
+         **{"batched_" + k.replace(":", "_"): x for k, x in c.items()})
+print(json.dumps({"hip": L.hip_runtime(), "torch_loaded": "torch" in sys.modules}))
+"""
+
+
+def test_library_alone_binds_its_own_runtime_and_matches_the_oracle(tmp_path):
+    out = tmp_path / "own.npz"
+    env = dict(os.environ, LAGMEAN_HIP_RUNTIME="own")
+    code = f"ROOT = {ROOT!r}\nOUT = {str(out)!r}\n" + CHILD
+    say("child process without torch (LAGMEAN_HIP_RUNTIME=own)")
+    p = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                       text=True, timeout=240)
+    say(p.stdout[-2000:])
+    assert p.returncode == 0, p.stdout[-4000:]
+    info = json.loads(p.stdout.strip().splitlines()[-1])
+    assert info["torch_loaded"] is False
+    assert info["hip"]["same"], info["hip"]        # built and bound HIP minor versions agree
+    assert not any("torch" in f for f in info["hip"]["runtime_files"]), info["hip"]
+    from synth import workload
+    w = workload("sw64_fp64")
+    _, ref = oracle_run(w, steps_per_interval=40, n_intervals=1)
+    g = np.load(out)
+    for key in OUTPUT_KEYS:
+        name = key.replace(":", "_")
+        assert np.array_equal(g[f"single_{name}"], g[f"batched_{name}"]), key
+        e = compare_value(key, g[f"single_{name}"], ref[0][key])
+        assert e < 1e-12, (key, e)
