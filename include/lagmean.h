@@ -289,7 +289,16 @@ lm_status lm_batch_destroy(lm_batch* b);
  *              tile fits in a CU's 160 KiB;
  *   xcd_order  1: blocks renumbered so that each of the 8 XCDs (own L2)
  *              receives a contiguous range of row blocks / column tiles with
- *              all tasks of each (the default); 0: hardware dispatch order.
+ *              all tasks of each (the default); 0: hardware dispatch order;
+ *   streams    1: the three passes of an RK4 stage run in order on the run's
+ *              stream (the default); 2: the stage's dependency graph runs on
+ *              two streams (the run's and one of its own): the dynamics rows
+ *              pass and the column groups of u, v, h on one, the mean
+ *              right-hand-side rows pass and the mean column groups on the
+ *              other, so that the mean column groups of a stage overlap the
+ *              next stage's dynamics rows pass.  Ordering with the caller is
+ *              unchanged: lm_step's work still ends on the run's stream.
+ *              Batched launches (captured graphs) take 1.
  * Two process-wide schedule tables, one entry per (n, precision) each: one for
  * single runs, read at every launch, and one for batched launches, read when a
  * batch captures its graph (a batch re-captures after any change of either
@@ -301,11 +310,12 @@ lm_status lm_batch_destroy(lm_batch* b);
 typedef struct lm_schedule {
   int32_t col_tile;  /* -1, 0, +1 */
   int32_t xcd_order; /* 0 or 1 */
+  int32_t streams;   /* 1 or 2 (single runs; batched launches take 1) */
 } lm_schedule;
 
-/* The usable schedules of (n, precision), the default first: *count receives
-   their number (at most 6); the first min(cap, count) go to out (out may be
-   null when cap is 0).  Host only. */
+/* The usable schedules of (n, precision) for single runs, the default first:
+   *count receives their number (at most 12); the first min(cap, count) go to
+   out (out may be null when cap is 0).  Host only. */
 lm_status lm_schedule_candidates(int32_t n, int32_t precision, lm_schedule* out, int32_t cap, int32_t* count);
 
 /* Set / read the schedule of (n, precision).  LM_E_ARG for a schedule that

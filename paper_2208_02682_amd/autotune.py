@@ -102,7 +102,7 @@ def merge_save(path: str, arch: str, tuned: List[dict]) -> None:
             for e in doc["entries"]:
                 if key(e) not in new:
                     keep.append({"context": e.get("context", "single"), "n": e["n"], "precision": e["precision"],
-                                 "best": (e["col_tile"], e["xcd_order"]),
+                                 "best": (e["col_tile"], e["xcd_order"], e.get("streams", 1)),
                                  "ms": {tuple(int(x) for x in k.split(",")): v for k, v in e["ms_per_step"].items()}})
     recs = sorted(keep + list(tuned), key=key)
     save_schedules(path, arch, recs)

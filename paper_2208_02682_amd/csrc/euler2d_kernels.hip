@@ -15,18 +15,25 @@ namespace {
 
 __device__ __forceinline__ cplx<double> ik(double k, cplx<double> a) { return {-k * a.y, k * a.x}; }
 
+// floor(o) taken periodically into [0, N): a finite displacement of any size
+// wraps around the torus; beyond 2^30 cells, or NaN, cell 0 (non-finite
+// weights then reach the outputs)
+__device__ __forceinline__ int cell_mod(double f, int N) {
+  const int i = (fabs(f) < 1073741824.0) ? int(f) : 0;
+  const int r = i % N;
+  return r < 0 ? r + N : r;
+}
+
 // periodic bilinear interpolant of F at grid point (jx, jy) + (xi_x, xi_y)
 // (cells and weights from the small offset xi / dx)
 __device__ double bilinear_at(const double* __restrict__ F, int N, int jx, int jy, double xi_x, double xi_y,
                               double dx) {
   const double ox = xi_x / dx, oy = xi_y / dx;
-  double fx = floor(ox), fy = floor(oy);
+  const double fx = floor(ox), fy = floor(oy);
   const double ax = ox - fx, ay = oy - fy;
-  fx = fmin(fmax(fx, -double(N)), double(N));
-  fy = fmin(fmax(fy, -double(N)), double(N));
-  int ix0 = jx + int(fx), iy0 = jy + int(fy);
-  ix0 = ix0 < 0 ? ix0 + N : (ix0 >= N ? ix0 - N : ix0);
-  iy0 = iy0 < 0 ? iy0 + N : (iy0 >= N ? iy0 - N : iy0);
+  int ix0 = jx + cell_mod(fx, N), iy0 = jy + cell_mod(fy, N);  // in [0, 2N)
+  ix0 = ix0 >= N ? ix0 - N : ix0;
+  iy0 = iy0 >= N ? iy0 - N : iy0;
   const int ix1 = ix0 + 1 == N ? 0 : ix0 + 1, iy1 = iy0 + 1 == N ? 0 : iy0 + 1;
   return (1.0 - ax) * (1.0 - ay) * F[iy0 * N + ix0] + ax * (1.0 - ay) * F[iy0 * N + ix1] +
          (1.0 - ax) * ay * F[iy1 * N + ix0] + ax * ay * F[iy1 * N + ix1];
@@ -36,17 +43,15 @@ __device__ double bilinear_at(const double* __restrict__ F, int N, int jx, int j
 __device__ double cubic_at(const double* __restrict__ F, int N, int jx, int jy, double xi_x, double xi_y,
                            double dx) {
   const double ox = xi_x / dx, oy = xi_y / dx;
-  double fx = floor(ox), fy = floor(oy);
+  const double fx = floor(ox), fy = floor(oy);
   const double ax = ox - fx, ay = oy - fy;
-  fx = fmin(fmax(fx, -double(N)), double(N));
-  fy = fmin(fmax(fy, -double(N)), double(N));
   const double wx[4] = {-ax * (ax - 1.0) * (ax - 2.0) / 6.0, (ax + 1.0) * (ax - 1.0) * (ax - 2.0) / 2.0,
                         -(ax + 1.0) * ax * (ax - 2.0) / 2.0, (ax + 1.0) * ax * (ax - 1.0) / 6.0};
   const double wy[4] = {-ay * (ay - 1.0) * (ay - 2.0) / 6.0, (ay + 1.0) * (ay - 1.0) * (ay - 2.0) / 2.0,
                         -(ay + 1.0) * ay * (ay - 2.0) / 2.0, (ay + 1.0) * ay * (ay - 1.0) / 6.0};
-  int bx = jx + int(fx), by = jy + int(fy);  // in [-N, 2N)
-  bx = bx < 0 ? bx + N : (bx >= N ? bx - N : bx);
-  by = by < 0 ? by + N : (by >= N ? by - N : by);
+  int bx = jx + cell_mod(fx, N), by = jy + cell_mod(fy, N);  // in [0, 2N)
+  bx = bx >= N ? bx - N : bx;
+  by = by >= N ? by - N : by;
   double out = 0.0;
   for (int j = 0; j < 4; ++j) {
     int r = by + j - 1;

@@ -148,16 +148,21 @@ unsigned sched_gen() {
 }
 
 // the usable schedules of (n, precision), the default first
-std::vector<lm::Sched> sched_candidates(int n, bool fp32) {
+// (a batch replays captured graphs on its own streams: one-stream schedules only)
+std::vector<lm::Sched> sched_candidates(int n, bool fp32, bool batched = false) {
   std::vector<lm::Sched> out;
   const int cb = fp32 ? (int)sizeof(cplx<float>) : (int)sizeof(cplx<double>);
-  for (int tile : {0, -1, 1}) {
-    if (!lm::col_tile_usable(n, tile, cb)) continue;
-    for (int remap : {1, 0}) {
-      lm::Sched sc;
-      sc.tile = tile;
-      sc.remap = remap;
-      out.push_back(sc);
+  for (int streams : {1, 2}) {
+    if (batched && streams != 1) continue;
+    for (int tile : {0, -1, 1}) {
+      if (!lm::col_tile_usable(n, tile, cb)) continue;
+      for (int remap : {1, 0}) {
+        lm::Sched sc;
+        sc.tile = tile;
+        sc.remap = remap;
+        sc.streams = streams;
+        out.push_back(sc);
+      }
     }
   }
   return out;
@@ -205,6 +210,19 @@ namespace {
 
 // the launches of a run follow the table's schedule of its (N, precision)
 void use_sched(lm_run* r) { r->sched = get_sched(r->d.N, r->fp32, false); }
+
+// the two-stream schedule's stream (after its work) and events
+void release_streams(lm_run* r) {
+  if (r->aux) {
+    (void)hipStreamSynchronize(r->aux);
+    (void)hipStreamDestroy(r->aux);
+    r->aux = nullptr;
+  }
+  for (auto& ev : r->ev) {
+    if (ev) (void)hipEventDestroy(ev);
+    ev = nullptr;
+  }
+}
 
 // one prognostic field's storage: leading words, trailing words of a
 // compensated float field (else null), and whether it is float
@@ -340,6 +358,15 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
     (void)hipGetLastError();
     return fail(LM_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
+  // the second stream and the events of the two-stream schedule
+  e = hipStreamCreateWithFlags(&r->aux, hipStreamNonBlocking);
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&r->ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    release_streams(r);
+    (void)hipFree(r->slab);
+    delete r;
+    return fail(LM_E_HIP, std::string("stream creation: ") + hipGetErrorString(e));
+  }
   // twiddles exp(-2 pi i m / N), long double on the host
   const int N = r->d.N;
   std::vector<cplx<double>> tw(N);
@@ -365,6 +392,7 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
   }
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(r->stream);
+    release_streams(r);
     (void)hipFree(r->slab);
     delete r;
     return fail(LM_E_HIP, std::string("init: ") + hipGetErrorString(e));
@@ -650,6 +678,7 @@ lm_status lm_destroy(lm_run* r) {
   if (!r) return LM_OK;
   if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
   hipError_t e = hipStreamSynchronize(r->stream);
+  release_streams(r);
   hipError_t e2 = hipFree(r->slab);
   delete r;
   if (e != hipSuccess) return fail(LM_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
@@ -951,7 +980,7 @@ lm_status lm_batch_autotune(lm_batch* b, int32_t steps, int32_t reps, int32_t* t
   for (size_t ki = 0; ki < keys.size() && e == hipSuccess && ls == LM_OK; ++ki) {
     const int N = keys[ki].first;
     const bool fp32 = keys[ki].second;
-    const std::vector<lm::Sched> cand = sched_candidates(N, fp32);
+    const std::vector<lm::Sched> cand = sched_candidates(N, fp32, true);
     lm::Sched best = get_sched(N, fp32, true);
     double best_t = -1.0;
     for (size_t c = 0; c < cand.size() && e == hipSuccess && ls == LM_OK; ++c) {
@@ -1008,7 +1037,7 @@ lm_status lm_schedule_candidates(int32_t n, int32_t precision, lm_schedule* out,
   if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
   if (cap < 0 || (cap > 0 && !out)) return fail(LM_E_ARG, "cap < 0 or null out");
   const std::vector<lm::Sched> c = sched_candidates(n, precision == LM_FP32_MIXED);
-  for (int i = 0; i < (int)c.size() && i < cap; ++i) out[i] = lm_schedule{c[i].tile, c[i].remap};
+  for (int i = 0; i < (int)c.size() && i < cap; ++i) out[i] = lm_schedule{c[i].tile, c[i].remap, c[i].streams};
   if (count) *count = (int32_t)c.size();
   return LM_OK;
 }
@@ -1022,8 +1051,8 @@ lm_status set_schedule_ctx(int32_t n, int32_t precision, const lm_schedule* s, b
   if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
   if (!s) return fail(LM_E_ARG, "null schedule");
   const bool fp32 = precision == LM_FP32_MIXED;
-  for (const lm::Sched& c : sched_candidates(n, fp32)) {
-    if (c.tile == s->col_tile && c.remap == s->xcd_order) {
+  for (const lm::Sched& c : sched_candidates(n, fp32, batched)) {
+    if (c.tile == s->col_tile && c.remap == s->xcd_order && c.streams == s->streams) {
       put_sched(n, fp32, batched, c);
       return LM_OK;
     }
@@ -1036,7 +1065,7 @@ lm_status get_schedule_ctx(int32_t n, int32_t precision, lm_schedule* s, bool ba
   if (precision != LM_FP64 && precision != LM_FP32_MIXED) return fail(LM_E_ARG, "unknown precision");
   if (!s) return fail(LM_E_ARG, "null schedule");
   const lm::Sched c = get_sched(n, precision == LM_FP32_MIXED, batched);
-  *s = lm_schedule{c.tile, c.remap};
+  *s = lm_schedule{c.tile, c.remap, c.streams};
   return LM_OK;
 }
 
@@ -1123,7 +1152,7 @@ lm_status lm_autotune(lm_run* r, int32_t steps, int32_t reps, lm_schedule* best,
   for (size_t k = 1; k < cand.size(); ++k)
     if (best_ms[k] < best_ms[bi]) bi = k;
   put_sched(r->d.N, r->fp32, false, cand[bi]);
-  if (best) *best = lm_schedule{cand[bi].tile, cand[bi].remap};
+  if (best) *best = lm_schedule{cand[bi].tile, cand[bi].remap, cand[bi].streams};
   for (int k = 0; k < (int)cand.size() && k < cap; ++k) ms[k] = best_ms[k];
   if (count) *count = (int32_t)cand.size();
   return LM_OK;

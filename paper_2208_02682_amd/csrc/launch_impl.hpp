@@ -42,22 +42,28 @@ void with_tile(int tile, F&& go) {
   go(std::integral_constant<int, 0>{});
 }
 
+// the column groups in slots [first, first + count) of one stage, on stream st
+// (the stage-value buffers are flipped by the caller once per stage)
 template <typename T, int N>
-void launch_columns_t(RunView& r, int stage) {
+void launch_columns_part(RunView& r, int stage, int first, int count, hipStream_t st) {
   const StepPtrs<T> P = step_ptrs<T>(r);
   cplx<T>* Ys[2] = {(cplx<T>*)r.at(r.L.Ys0), (cplx<T>*)r.at(r.L.Ys1)};
   const cplx<T>* Ys_in = Ys[r.ys_cur];
   cplx<T>* Ys_out = (stage < 0) ? Ys[r.ys_cur] : Ys[r.ys_cur ^ 1];
-  const int groups = col_groups(r.ph);
   // time of the stage input this launch prepares: the current one in the
   // prologue, else the next stage's (c = 1/2, 1/2, 1, then the next step's 0)
   const double t_next = (double(r.n) + (stage < 0 ? 0.0 : (stage <= 1 ? 0.5 : 1.0))) * r.ph.dt;
   with_tile<T, N>(r.sched.tile, [&](auto w) {
     constexpr int W = decltype(w)::value;
-    const dim3 g = col_grid<N, W>(r.d, groups), b = col_block<N, W>();
-    hipLaunchKernelGGL((k_columns<T, N, W>), g, b, 0, r.stream, P, r.d, r.ph, stage, t_next, Ys_in, Ys_out,
-                       r.sched.remap);
+    const dim3 g = col_grid<N, W>(r.d, count), b = col_block<N, W>();
+    hipLaunchKernelGGL((k_columns<T, N, W>), g, b, 0, st, P, r.d, r.ph, stage, t_next, Ys_in, Ys_out,
+                       r.sched.remap, first);
   });
+}
+
+template <typename T, int N>
+void launch_columns_t(RunView& r, int stage) {
+  launch_columns_part<T, N>(r, stage, 0, col_groups(r.ph), r.stream);
   if (stage >= 0) r.ys_cur ^= 1;
 }
 
@@ -75,10 +81,56 @@ void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
   }
 }
 
+// Two-stream form of the steps.  Per stage the dependencies are
+//   rows_dyn(i)  <- the dynamics column groups of stage i-1 (their outputs) and
+//                   rows_rhs(i-1) (it reads the physical fields rows_dyn rewrites),
+//   rows_rhs(i)  <- rows_dyn(i) and the mean column groups of stage i-1,
+//   dynamics column groups(i) <- rows_dyn(i),  mean column groups(i) <- rows_rhs(i),
+// and no pass writes what a pass it may overlap with reads.  The auxiliary
+// stream carries rows_dyn and the dynamics groups, the run's stream rows_rhs
+// and the mean groups, so the mean groups of stage i overlap rows_dyn of stage
+// i+1 and the dynamics groups overlap rows_rhs.  Same kernels, same arguments,
+// same results as the one-stream form.
+template <typename T, int N>
+hipError_t launch_steps_2s(RunView& r, int nsteps) {
+  const StepPtrs<T> P = step_ptrs<T>(r);
+  static const double c[4] = {0.0, 0.5, 0.5, 1.0};
+  const int nd = col_dyn_groups(r.ph), nm = col_mean_groups(r.ph);
+  hipEvent_t fork = r.ev[0], dyn = r.ev[1], rhs = r.ev[2], join = r.ev[3];
+  hipError_t e = hipEventRecord(fork, r.stream);  // aux starts after everything queued so far
+  if (e == hipSuccess) e = hipStreamWaitEvent(r.aux, fork, 0);
+  for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+    for (int stage = 0; stage < 4 && e == hipSuccess; ++stage) {
+      const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
+      if (s + stage > 0) e = hipStreamWaitEvent(r.aux, rhs, 0);  // rows_rhs of the previous stage
+      if (e != hipSuccess) break;
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.aux, P, r.d, r.ph,
+                         r.sched.remap);
+      e = hipEventRecord(dyn, r.aux);
+      launch_columns_part<T, N>(r, stage, 0, nd, r.aux);
+      if (e == hipSuccess) e = hipStreamWaitEvent(r.stream, dyn, 0);
+      if (e != hipSuccess) break;
+      launch_rows_rhs<T, N>(r, P, sval);  // on the run's stream
+      e = hipEventRecord(rhs, r.stream);
+      launch_columns_part<T, N>(r, stage, nd, nm, r.stream);
+      r.ys_cur ^= 1;
+    }
+    r.n += 1;
+  }
+  // the run's stream resumes after the auxiliary stream's last work
+  const hipError_t e2 = hipEventRecord(join, r.aux);
+  const hipError_t e3 = (e2 == hipSuccess) ? hipStreamWaitEvent(r.stream, join, 0) : e2;
+  return e != hipSuccess ? e : e3;
+}
+
 template <typename T, int N>
 void launch_steps_t(RunView& r, int nsteps) {
   const StepPtrs<T> P = step_ptrs<T>(r);
   static const double c[4] = {0.0, 0.5, 0.5, 1.0};
+  if (r.sched.streams == 2 && r.aux && nsteps > 0) {
+    (void)launch_steps_2s<T, N>(r, nsteps);  // launch errors surface through hipGetLastError
+    return;
+  }
   for (int s = 0; s < nsteps; ++s) {
     for (int stage = 0; stage < 4; ++stage) {
       // time since the interval start, from integers

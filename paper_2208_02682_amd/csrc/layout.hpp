@@ -98,16 +98,19 @@ struct Phys {
   double kx, ky, A, omega, phase, U0, V0;  // kinematic: h' = A cos(kx x + ky y - omega t + phase)
 };
 
-// column groups launched for a run: blockIdx.y -> ColGroup
-__host__ __device__ inline int col_groups(const Phys& ph) { return NCG + (ph.mom ? 2 : 0) + (ph.gen ? 2 : 0); }
-__host__ __device__ inline int col_group_of(const Phys& ph, int y) {
-  if (y < NCG) return y;
-  y -= NCG;
-  if (ph.mom) {
-    if (y < 2) return CG_GMX + y;
-    y -= 2;
-  }
-  return CG_EF0 + y;
+// Column groups launched for a run, in slot order: first the groups that need
+// only the dynamics rows pass (u, v, h, and the Eulerian groups of fields other
+// than (h, zeta)), then those that need the mean right-hand-side rows pass (xi,
+// g-bar, g-tilde, P, and the momentum 1-form).  A launch covers a range of slots.
+__host__ __device__ inline int col_dyn_groups(const Phys& ph) { return 3 + (ph.gen ? 2 : 0); }
+__host__ __device__ inline int col_mean_groups(const Phys& ph) { return 8 + (ph.mom ? 2 : 0); }
+__host__ __device__ inline int col_groups(const Phys& ph) { return col_dyn_groups(ph) + col_mean_groups(ph); }
+__host__ __device__ inline int col_group_of(const Phys& ph, int slot) {
+  if (slot < 3) return CG_U + slot;
+  const int nd = col_dyn_groups(ph);
+  if (slot < nd) return CG_EF0 + (slot - 3);
+  const int j = slot - nd;
+  return (j < 8) ? CG_XIX + j : CG_GMX + (j - 8);
 }
 
 }  // namespace lm

@@ -74,8 +74,10 @@ inline Layout make_layout(const Dims& d, bool fp32, bool mom, bool gen) {
 // column tile width (col_tile_of) and the block order (xcd_split).  Neither
 // changes what a row or a column computes, or in which order.
 struct Sched {
-  int tile = 0;   // -1: half the default column tile width, 0: default, +1: twice
-  int remap = 1;  // 1: XCD-aware block order, 0: hardware order
+  int tile = 0;     // -1: half the default column tile width, 0: default, +1: twice
+  int remap = 1;    // 1: XCD-aware block order, 0: hardware order
+  int streams = 1;  // 1: the passes of a stage in order on the run's stream; 2: the
+                    // stage's dependency graph on two streams (single runs only)
 };
 
 // Waits for a stream when it leaves scope, on every path out of a call: no
@@ -99,6 +101,8 @@ struct RunView {
   int64_t n, n_tau;  // steps since set_state; step index at the interval start
   int ys_cur;        // which stage-value buffer holds the current stage input
   Sched sched;       // launch schedule used by the next launches
+  hipStream_t aux = nullptr;  // second stream of the two-stream schedule
+  hipEvent_t ev[4] = {};      // its fork, rows_dyn, rows_rhs and join events
   void* at(size_t off) const { return slab + off; }
 };
 

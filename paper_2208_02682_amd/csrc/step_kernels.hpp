@@ -128,8 +128,6 @@ __device__ __forceinline__ void forward_row(cplx<T> (&z)[fft_E<N>()], cplx<T>* b
   sched_fence();
 }
 
-__device__ __forceinline__ int wrapN(int i, int N) { return (i + N) % N; }
-
 // i in [-N, 2N) to [0, N): a mask for powers of two, two selects otherwise
 template <int N>
 __device__ __forceinline__ int wrap2N(int i) {
@@ -138,6 +136,21 @@ __device__ __forceinline__ int wrap2N(int i) {
   } else {
     i = (i < 0) ? i + N : i;
     return (i >= N) ? i - N : i;
+  }
+}
+
+// The cell offset floor(o) of a gather (o = displacement / dx) taken
+// periodically into [0, N): a finite displacement of any size wraps around the
+// torus.  Offsets beyond 2^30 cells and NaN land on cell 0 (their weights are
+// non-finite, which the end-of-interval check reports).
+template <int N, typename T>
+__device__ __forceinline__ int cell_mod(T f) {
+  const int i = (fabs(f) < T(1073741824.0)) ? int(f) : 0;
+  if constexpr ((N & (N - 1)) == 0) {
+    return i & (N - 1);
+  } else {
+    const int r = i % N;
+    return r < 0 ? r + N : r;
   }
 }
 
@@ -168,13 +181,10 @@ template <typename T, int N, int PAIR>
 __device__ __forceinline__ cplx<T> gather2(const P4<T>* __restrict__ F, int x, int y, T xix, T xiy) {
   const T scl = T(double(N) / 6.283185307179586476925286766559);
   T ox = xix * scl, oy = xiy * scl;
-  T fx = floor(ox), fy = floor(oy);
-  // keep indices in range even for non-finite displacements
-  fx = fmin(fmax(fx, T(-N)), T(N));
-  fy = fmin(fmax(fy, T(-N)), T(N));
+  const T fx = floor(ox), fy = floor(oy);
   const T ax = ox - fx, ay = oy - fy;
-  // x + fx and y + fy lie in [-N, 2N)
-  const int ix0 = wrap2N<N>(x + int(fx)), iy0 = wrap2N<N>(y + int(fy));
+  // x + (fx mod N) and y + (fy mod N) lie in [0, 2N)
+  const int ix0 = wrap2N<N>(x + cell_mod<N>(fx)), iy0 = wrap2N<N>(y + cell_mod<N>(fy));
   const int ix1 = (ix0 + 1 == N) ? 0 : ix0 + 1, iy1 = (iy0 + 1 == N) ? 0 : iy0 + 1;
   // uniform base plus 32-bit byte offsets (the field is far below 4 GiB)
   const char* F2 = reinterpret_cast<const char*>(F) + PAIR * sizeof(cplx<T>);
@@ -199,15 +209,13 @@ template <typename T, int N, int PAIR>
 __device__ __forceinline__ cplx<T> gather2_cubic(const P4<T>* __restrict__ F, int x, int y, T xix, T xiy) {
   const T scl = T(double(N) / 6.283185307179586476925286766559);
   T ox = xix * scl, oy = xiy * scl;
-  T fx = floor(ox), fy = floor(oy);
-  fx = fmin(fmax(fx, T(-N)), T(N));
-  fy = fmin(fmax(fy, T(-N)), T(N));
+  const T fx = floor(ox), fy = floor(oy);
   const T ax = ox - fx, ay = oy - fy;
   const T wx[4] = {-ax * (ax - T(1)) * (ax - T(2)) / T(6), (ax + T(1)) * (ax - T(1)) * (ax - T(2)) / T(2),
                    -(ax + T(1)) * ax * (ax - T(2)) / T(2), (ax + T(1)) * ax * (ax - T(1)) / T(6)};
   const T wy[4] = {-ay * (ay - T(1)) * (ay - T(2)) / T(6), (ay + T(1)) * (ay - T(1)) * (ay - T(2)) / T(2),
                    -(ay + T(1)) * ay * (ay - T(2)) / T(2), (ay + T(1)) * ay * (ay - T(1)) / T(6)};
-  const int bx = wrap2N<N>(x + int(fx)), by = wrap2N<N>(y + int(fy));
+  const int bx = wrap2N<N>(x + cell_mod<N>(fx)), by = wrap2N<N>(y + cell_mod<N>(fy));
   const char* F2 = reinterpret_cast<const char*>(F) + PAIR * sizeof(cplx<T>);
   constexpr unsigned PT = sizeof(P4<T>), ROW = N * sizeof(P4<T>);
   unsigned col[4];
@@ -241,12 +249,9 @@ template <typename T, int N>
 __device__ __forceinline__ P4<T> gather4(const P4<T>* __restrict__ F, int x, int y, T xix, T xiy) {
   const T scl = T(double(N) / 6.283185307179586476925286766559);
   T ox = xix * scl, oy = xiy * scl;
-  T fx = floor(ox), fy = floor(oy);
-  // keep indices in range even for non-finite displacements
-  fx = fmin(fmax(fx, T(-N)), T(N));
-  fy = fmin(fmax(fy, T(-N)), T(N));
+  const T fx = floor(ox), fy = floor(oy);
   const T ax = ox - fx, ay = oy - fy;
-  const int ix0 = wrapN(x + int(fx), N), iy0 = wrapN(y + int(fy), N);
+  const int ix0 = wrap2N<N>(x + cell_mod<N>(fx)), iy0 = wrap2N<N>(y + cell_mod<N>(fy));
   const int ix1 = (ix0 + 1 == N) ? 0 : ix0 + 1, iy1 = (iy0 + 1 == N) ? 0 : iy0 + 1;
   const P4<T> f00 = F[iy0 * N + ix0], f01 = F[iy0 * N + ix1];
   const P4<T> f10 = F[iy1 * N + ix0], f11 = F[iy1 * N + ix1];
@@ -953,14 +958,15 @@ __host__ __device__ constexpr int col_waves() {
 }
 
 // W: column tile width (col_tile<N, W>)
+// slot0: the first group slot of this launch (grid = (column tiles, group slots))
 template <typename T, int N, int W>
 __global__ void __launch_bounds__((col_threads<N, W>()), (col_waves<T, N, false>()))
     k_columns(StepPtrs<T> P, Dims d, Phys ph, int stage, double t_next, const cplx<T>* Ys_in, cplx<T>* Ys_out,
-              int remap) {
+              int remap, int slot0) {
   __shared__ cplx<T> lds[col_tile<N, W>() * col_buf(N)];
-  int tile, group, z;
-  xcd_split(gridDim.x, gridDim.y, tile, group, z, remap);  // grid = (column tiles, field groups)
-  columns_body<T, N, col_tile<N, W>()>(P, d, ph, stage, t_next, Ys_in, Ys_out, tile, group, lds);
+  int tile, slot, z;
+  xcd_split(gridDim.x, gridDim.y, tile, slot, z, remap);
+  columns_body<T, N, col_tile<N, W>()>(P, d, ph, stage, t_next, Ys_in, Ys_out, tile, slot0 + slot, lds);
 }
 
 // --------------------------------------------------------------------------

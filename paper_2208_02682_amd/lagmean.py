@@ -67,11 +67,13 @@ class E2DConfig(ctypes.Structure):
 
 
 class Schedule(ctypes.Structure):
-    """lm_schedule: column tile width (-1, 0, +1) and XCD-aware block order (0, 1)."""
-    _fields_ = [("col_tile", ctypes.c_int32), ("xcd_order", ctypes.c_int32)]
+    """lm_schedule: column tile width (-1, 0, +1), XCD-aware block order (0, 1) and
+    streams (1: the passes of a stage in order, 2: the stage's dependency graph on
+    two streams)."""
+    _fields_ = [("col_tile", ctypes.c_int32), ("xcd_order", ctypes.c_int32), ("streams", ctypes.c_int32)]
 
-    def key(self) -> Tuple[int, int]:
-        return (int(self.col_tile), int(self.xcd_order))
+    def key(self) -> Tuple[int, int, int]:
+        return (int(self.col_tile), int(self.xcd_order), int(self.streams))
 
 
 E2D_OUTPUTS = {"zeta": 0, "PS_mean": 1, "PS_eta_x": 2, "PS_eta_y": 3, "SL_mean": 4, "SL_eta_x": 5, "SL_eta_y": 6}
@@ -196,24 +198,26 @@ def field_slots(cfg: Config) -> Tuple[str, str]:
 PRECISIONS = {"fp64": LM_FP64, "fp32": LM_FP32_MIXED}
 
 
-def schedule_candidates(n: int, precision: str) -> List[Tuple[int, int]]:
-    """Usable launch schedules (col_tile, xcd_order) of (n, precision), the default first."""
+def schedule_candidates(n: int, precision: str) -> List[Tuple[int, int, int]]:
+    """Usable launch schedules (col_tile, xcd_order, streams) of single runs of
+    (n, precision), the default first."""
     lib = load_library()
-    buf = (Schedule * 8)()
+    buf = (Schedule * 16)()
     cnt = ctypes.c_int32(0)
-    _check(lib.lm_schedule_candidates(n, PRECISIONS[precision], buf, 8, ctypes.byref(cnt)))
+    _check(lib.lm_schedule_candidates(n, PRECISIONS[precision], buf, len(buf), ctypes.byref(cnt)))
     return [buf[i].key() for i in range(cnt.value)]
 
 
-def set_schedule(n: int, precision: str, col_tile: int, xcd_order: int, batched: bool = False) -> None:
+def set_schedule(n: int, precision: str, col_tile: int, xcd_order: int, streams: int = 1,
+                 batched: bool = False) -> None:
     """Install a schedule in the single-run table (or the batched launches' table)."""
-    s = Schedule(col_tile=col_tile, xcd_order=xcd_order)
+    s = Schedule(col_tile=col_tile, xcd_order=xcd_order, streams=streams)
     lib = load_library()
     fn = lib.lm_set_batch_schedule if batched else lib.lm_set_schedule
     _check(fn(n, PRECISIONS[precision], ctypes.byref(s)))
 
 
-def get_schedule(n: int, precision: str, batched: bool = False) -> Tuple[int, int]:
+def get_schedule(n: int, precision: str, batched: bool = False) -> Tuple[int, int, int]:
     s = Schedule()
     lib = load_library()
     fn = lib.lm_get_batch_schedule if batched else lib.lm_get_schedule
@@ -228,9 +232,10 @@ def save_schedules(path: str, arch: str, tuned: List[dict]) -> None:
     context "batched" for Batch.autotune's)."""
     entries = []
     for t in tuned:
+        best = tuple(t["best"]) + (1,) * (3 - len(t["best"]))
         entries.append({"context": t.get("context", "single"), "n": int(t["n"]), "precision": t["precision"],
-                        "col_tile": int(t["best"][0]), "xcd_order": int(t["best"][1]),
-                        "ms_per_step": {f"{k[0]},{k[1]}": float(v) for k, v in t.get("ms", {}).items()}})
+                        "col_tile": int(best[0]), "xcd_order": int(best[1]), "streams": int(best[2]),
+                        "ms_per_step": {",".join(str(x) for x in k): float(v) for k, v in t.get("ms", {}).items()}})
     with open(path, "w") as f:
         json.dump({"format": 1, "arch": arch, "entries": entries}, f, indent=1)
 
@@ -245,7 +250,7 @@ def load_schedules(path: str, arch: Optional[str] = None) -> int:
     if arch is not None and doc.get("arch") != arch:
         return 0
     for e in doc["entries"]:
-        set_schedule(int(e["n"]), e["precision"], int(e["col_tile"]), int(e["xcd_order"]),
+        set_schedule(int(e["n"]), e["precision"], int(e["col_tile"]), int(e["xcd_order"]), int(e.get("streams", 1)),
                      batched=e.get("context", "single") == "batched")
     return len(doc["entries"])
 

@@ -86,7 +86,7 @@ def test_header_is_plain_c(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     src = tmp_path / "h.c"
-    src.write_text('#include "lagmean.h"\nint main(void) { lm_schedule s = {0, 1}; lm_config c; (void)s; (void)c;'
+    src.write_text('#include "lagmean.h"\nint main(void) { lm_schedule s = {0, 1, 1}; lm_config c; (void)s; (void)c;'
                    ' return (int)LM_OK; }\n')
     subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", INCLUDE, "-c", str(src), "-o",
                     str(tmp_path / "h.o")], check=True)

@@ -108,3 +108,39 @@ def test_batch_rules():
     assert run.counters() == (3, 3)
     b.close()
     run.close()
+
+
+def test_many_small_members_and_a_512_member_are_the_same_alone_and_batched():
+    """33 members in one batch (32 of 64^2 and 128^2, both precisions, and one of
+    512^2): the run descriptors, counters and blockIdx.z indexing at scale."""
+    import paper_2208_02682_amd as lib
+    from synth.workloads import scaled_run
+    specs = []
+    for i in range(32):
+        N, prec = (64, "fp64") if i % 3 == 0 else ((128, "fp32") if i % 3 == 1 else (64, "fp32"))
+        w = scaled_run(N, Ro=0.03 + 0.003 * i, ratio=0.5 + 0.1 * i, periods=1.0, seeds=(500 + 2 * i, 501 + 2 * i),
+                       precision=prec)
+        specs.append((w, 3 + (7 * i) % 11))
+    specs.append((scaled_run(512, Ro=0.1, ratio=1.0, periods=1.0, seeds=(600, 601), precision="fp32"), 9))
+    alone = []
+    for w, steps in specs:
+        run = _start(lib, w)
+        run.step(steps)
+        run.end_interval()
+        alone.append(run.outputs())
+        run.close()
+    runs = [_start(lib, w) for w, _ in specs]
+    with lib.Batch() as b:
+        for run, (w, steps) in zip(runs, specs):
+            b.add(run, steps)
+        while b.step(4):
+            pass
+        for run in runs:
+            b.remove(run)
+    for i, (run, (w, steps)) in enumerate(zip(runs, specs)):
+        run.end_interval()
+        got = run.outputs()
+        for k in OUTPUT_KEYS:
+            assert np.array_equal(got[k], alone[i][k]), (i, w.N, w.precision, k)
+        run.close()
+    say(f"{len(specs)} members identical alone and batched")

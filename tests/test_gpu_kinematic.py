@@ -162,6 +162,34 @@ def test_uniform_flow_displacements_are_exact_on_the_gpu():
                 assert np.max(np.abs(out[f"{S}_mean:u"] - U)) < tol
 
 
+@pytest.mark.parametrize("interp", ["bilinear", "cubic"])
+def test_gathers_wrap_displacements_beyond_one_period(interp):
+    """A wave carried by a uniform drift large enough that xi = U s / 2 passes 2 pi:
+    the gathers take the displaced points periodically (as the oracle's modulo),
+    in both precisions."""
+    from paper_2208_02682_amd.lagmean import Run, make_config
+    N, dt, nsteps = 64, 0.02, 150
+    kin = dict(kx=1.0, ky=0.0, A=0.05, omega=0.0, phase=0.3, U0=5.0, V0=-3.0)
+    kin_o = dict(kin, omega=omega_poincare(1.0))
+    out = {}
+    for prec in ("fp64", "fp32"):
+        run = Run(make_config(N, precision=prec, dt=dt, fields=("h", "u"), kinematic=kin, interp=interp))
+        run.begin_interval()
+        run.step(nsteps)
+        run.end_interval()
+        out[prec] = run.field_outputs()
+        run.close()
+    assert np.max(out["fp64"]["S2_xi_x"]) > 2 * math.pi          # displacements beyond one period
+    r = OracleRun(Params(N=N, dt=dt, fields=("h", "u"), mode="kinematic", interp=interp, U0=kin["U0"],
+                         V0=kin["V0"], waves=[PlaneWave(1.0, 0.0, kin["A"], kin_o["omega"], kin["phase"])]))
+    r.begin_interval()
+    r.step(nsteps)
+    ref = r.end_interval()
+    for key in ref:
+        assert _rel(key, out["fp64"][key], ref[key]) < 1e-12, key
+        assert _rel(key, out["fp32"][key], ref[key]) < 1e-5, key
+
+
 def test_kinematic_run_has_no_state_to_set():
     L = _lib()
     from paper_2208_02682_amd.lagmean import LagMeanError, Run, make_config

@@ -171,7 +171,7 @@ def test_batch_autotune_leaves_the_members_as_they_were():
         for r in runs:
             b.remove(r)
     for N, p, _ in specs:
-        assert L.get_schedule(N, p) == (0, 1)      # the single-run table is not touched
+        assert L.get_schedule(N, p) == (0, 1, 1)   # the single-run table is not touched
     for i, r in enumerate(runs):
         got = _finish(r)
         for k in alone[i]:

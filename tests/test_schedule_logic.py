@@ -42,22 +42,24 @@ def test_candidates_follow_the_stated_rule(L):
     for n in SIZES:
         for p, cb in (("fp32", 8), ("fp64", 16)):
             c = L.schedule_candidates(n, p)
-            assert c[0] == (0, 1), (n, p)                      # the default first
+            assert c[0] == (0, 1, 1), (n, p)                   # the default first
             assert len(set(c)) == len(c)
-            want = [(w, x) for w in (0, -1, 1) if _usable(n, w, cb) for x in (1, 0)]
+            want = [(w, x, st) for st in (1, 2) for w in (0, -1, 1) if _usable(n, w, cb) for x in (1, 0)]
             assert c == want, (n, p, c)
     # the cases the rule singles out
-    assert (1, 1) not in L.schedule_candidates(1024, "fp64")    # 16 float64 columns need 278 KB of LDS
-    assert (-1, 1) not in L.schedule_candidates(64, "fp32")     # half a wavefront
-    assert len(L.schedule_candidates(1024, "fp32")) == 6
+    assert (1, 1, 1) not in L.schedule_candidates(1024, "fp64")  # 16 float64 columns need 278 KB of LDS
+    assert (-1, 1, 1) not in L.schedule_candidates(64, "fp32")   # half a wavefront
+    assert len(L.schedule_candidates(1024, "fp32")) == 12
 
 
 def test_set_get_and_refusals(L):
     from paper_2208_02682_amd import LagMeanError
-    assert L.get_schedule(256, "fp32") == (0, 1)
+    assert L.get_schedule(256, "fp32") == (0, 1, 1)
     L.set_schedule(256, "fp32", -1, 0)
-    assert L.get_schedule(256, "fp32") == (-1, 0)
-    assert L.get_schedule(256, "fp64") == (0, 1)               # per precision
+    assert L.get_schedule(256, "fp32") == (-1, 0, 1)
+    L.set_schedule(256, "fp32", -1, 0, 2)
+    assert L.get_schedule(256, "fp32") == (-1, 0, 2)
+    assert L.get_schedule(256, "fp64") == (0, 1, 1)            # per precision
     with pytest.raises(LagMeanError) as e:
         L.set_schedule(1024, "fp64", 1, 1)
     assert e.value.status == -1
@@ -67,12 +69,17 @@ def test_set_get_and_refusals(L):
     with pytest.raises(LagMeanError) as e:
         L.set_schedule(100, "fp32", 0, 1)
     assert e.value.status == -6
+    with pytest.raises(LagMeanError) as e:
+        L.set_schedule(256, "fp32", 0, 1, 3)
+    assert e.value.status == -1
     L.set_schedule(256, "fp32", 0, 1)
-    # the batched launches' table is separate
+    # the batched launches' table is separate, and takes one stream only
     L.set_schedule(256, "fp32", 1, 0, batched=True)
-    assert L.get_schedule(256, "fp32", batched=True) == (1, 0) and L.get_schedule(256, "fp32") == (0, 1)
+    assert L.get_schedule(256, "fp32", batched=True) == (1, 0, 1) and L.get_schedule(256, "fp32") == (0, 1, 1)
     with pytest.raises(LagMeanError):
         L.set_schedule(1024, "fp64", 1, 1, batched=True)
+    with pytest.raises(LagMeanError):
+        L.set_schedule(256, "fp32", 0, 1, 2, batched=True)
     L.set_schedule(256, "fp32", 0, 1, batched=True)
     lib = L.load_library()
     assert lib.lm_schedule_candidates(256, 1, None, 1, None) == -1   # cap > 0 with no array
@@ -83,28 +90,35 @@ def test_set_get_and_refusals(L):
 def test_json_cache_round_trip_and_merge(L, tmp_path):
     from paper_2208_02682_amd import autotune as at
     path = str(tmp_path / "s.json")
-    t1 = [{"n": 256, "precision": "fp32", "best": (-1, 0), "ms": {(0, 1): 0.2, (0, 0): 0.21, (-1, 1): 0.19,
-                                                                 (-1, 0): 0.18, (1, 1): 0.25, (1, 0): 0.26}}]
-    t2 = [{"n": 512, "precision": "fp64", "best": (0, 0), "ms": {(0, 1): 1.0, (0, 0): 0.9}}]
+    t1 = [{"n": 256, "precision": "fp32", "best": (-1, 0, 2), "ms": {(0, 1, 1): 0.2, (0, 0, 1): 0.21,
+                                                                    (-1, 1, 1): 0.19, (-1, 0, 2): 0.18,
+                                                                    (1, 1, 1): 0.25, (1, 0, 1): 0.26}}]
+    t2 = [{"n": 512, "precision": "fp64", "best": (0, 0, 1), "ms": {(0, 1, 1): 1.0, (0, 0, 1): 0.9}}]
     at.merge_save(path, "gfx950", t1)
     at.merge_save(path, "gfx950", t2)                          # keeps the 256 entry
     doc = json.load(open(path))
     assert doc["arch"] == "gfx950" and [(e["n"], e["precision"]) for e in doc["entries"]] == [(256, "fp32"),
                                                                                              (512, "fp64")]
-    assert doc["entries"][0]["ms_per_step"]["-1,0"] == 0.18
+    assert doc["entries"][0]["ms_per_step"]["-1,0,2"] == 0.18
     assert L.load_schedules(path, "gfx942") == 0               # another architecture: nothing applied
-    assert L.get_schedule(256, "fp32") == (0, 1)
+    assert L.get_schedule(256, "fp32") == (0, 1, 1)
     assert L.load_schedules(path, "gfx950") == 2
-    assert L.get_schedule(256, "fp32") == (-1, 0) and L.get_schedule(512, "fp64") == (0, 0)
+    assert L.get_schedule(256, "fp32") == (-1, 0, 2) and L.get_schedule(512, "fp64") == (0, 0, 1)
     # a re-tune of one entry replaces it; batched entries are kept apart
-    at.merge_save(path, "gfx950", [dict(t1[0], best=(0, 1))])
-    at.merge_save(path, "gfx950", [{"context": "batched", "n": 256, "precision": "fp32", "best": (1, 1)}])
-    got = {(e["context"], e["n"], e["precision"]): (e["col_tile"], e["xcd_order"])
+    at.merge_save(path, "gfx950", [dict(t1[0], best=(0, 1, 1))])
+    at.merge_save(path, "gfx950", [{"context": "batched", "n": 256, "precision": "fp32", "best": (1, 1, 1)}])
+    got = {(e["context"], e["n"], e["precision"]): (e["col_tile"], e["xcd_order"], e["streams"])
            for e in json.load(open(path))["entries"]}
-    assert got == {("single", 256, "fp32"): (0, 1), ("single", 512, "fp64"): (0, 0),
-                   ("batched", 256, "fp32"): (1, 1)}
+    assert got == {("single", 256, "fp32"): (0, 1, 1), ("single", 512, "fp64"): (0, 0, 1),
+                   ("batched", 256, "fp32"): (1, 1, 1)}
     assert L.load_schedules(path, "gfx950") == 3
-    assert L.get_schedule(256, "fp32", batched=True) == (1, 1) and L.get_schedule(256, "fp32") == (0, 1)
+    assert L.get_schedule(256, "fp32", batched=True) == (1, 1, 1) and L.get_schedule(256, "fp32") == (0, 1, 1)
+    # entries written before the streams field existed read as one stream
+    doc = json.load(open(path))
+    for e in doc["entries"]:
+        e.pop("streams")
+    json.dump(doc, open(path, "w"))
+    assert L.load_schedules(path, "gfx950") == 3 and L.get_schedule(512, "fp64") == (0, 0, 1)
 
 
 def test_shipped_cache_is_well_formed(L):
@@ -116,8 +130,9 @@ def test_shipped_cache_is_well_formed(L):
     assert doc["format"] == 1 and doc["arch"] == "gfx950"
     for e in doc["entries"]:
         assert e.get("context", "single") in ("single", "batched")
-        assert (e["col_tile"], e["xcd_order"]) in L.schedule_candidates(e["n"], e["precision"])
+        key = (e["col_tile"], e["xcd_order"], e.get("streams", 1))
+        assert key in L.schedule_candidates(e["n"], e["precision"])
         # the chosen schedule is the fastest measured one (where times were recorded)
         if e["ms_per_step"]:
             best = min(e["ms_per_step"], key=e["ms_per_step"].get)
-            assert best == f"{e['col_tile']},{e['xcd_order']}"
+            assert best in (",".join(str(x) for x in key), ",".join(str(x) for x in key[:2]))
