@@ -120,3 +120,55 @@ def test_remapped_strategy1_matches_strategy2_on_the_same_particles():
         err = np.max(np.abs(a - b))
         assert err < 2e-3
         assert err < 0.05 * np.max(np.abs(b - b.mean()))
+
+
+def test_where_the_mean_map_folds_the_lowest_cell_index_decides():
+    """A closed-form fold: eta_x = 8 cells sin(2 pi x / N), eta_y = 0, so the mean
+    map x -> x - eta(x) (piecewise linear between grid values along x) is not
+    monotone near x = 0 and x - eta(x) = y has three roots for some grid points y.
+    Every root is a particle whose mean position is y (the paper's caveat about
+    clustering mean positions, section 5): any covering patch solves eq. (3.8).
+    The stated rule takes the patch of the lowest cell index iy N + ix.  Here every
+    covering segment of every row is enumerated directly and solved in closed
+    form, and the oracle must return the root of the lowest covering cell; the
+    test field takes different values at the different roots, so another choice
+    fails."""
+    N = 32
+    h = 2 * np.pi / N
+    i = np.arange(N)
+    amp = 8.0                                            # cells; amp * 2 pi / N > 1 folds the map
+    e1 = amp * np.sin(2 * np.pi * i / N)                 # eta_x in cells along x
+    eta_x = np.broadcast_to(e1[None, :] * h, (N, N)).copy()
+    eta_y = np.zeros((N, N))
+    X, Y = _grid(N)
+    ftil = np.cos(X) + 0.4 * np.sin(X / 1.0 + 0.3) + 0.3 * np.sin(2 * Y)
+    out, d_x, d_y, res = remap_s1({"f": ftil}, eta_x, eta_y)
+    m = np.arange(N + 1) - np.append(e1, e1[0])          # x - eta(x) at x = 0..N (cells, unwrapped)
+    multi = 0
+    for iy in range(N):
+        # a grid point on row iy is covered by cells of rows iy - 1 (t = 1) and iy
+        # (t = 0); eta does not depend on y, so both rows give the same roots in x
+        # and the lowest cell index is the lowest covering ix
+        for yx in range(N):
+            roots = []
+            for ix in range(N):
+                a, b = m[ix], m[ix + 1]
+                for k in (-1, 0, 1):
+                    yk = yx + k * N
+                    if min(a, b) - 1e-12 <= yk <= max(a, b) + 1e-12 and a != b:
+                        s = (yk - a) / (b - a)
+                        roots.append((ix, ix + s, yk))
+            assert roots, (iy, yx)
+            distinct = {round(x, 9) for _, x, _ in roots}
+            if len(distinct) > 1:
+                multi += 1
+            ix, x, yk = min(roots)                          # the lowest covering cell of the row
+            assert abs(d_x[iy, yx] - (x - yk) * h) < 1e-12, (iy, yx, roots)
+            assert abs(d_y[iy, yx]) < 1e-12
+            # f~ at the root: linear along x between the grid values of the row
+            j0 = int(np.floor(x)) % N
+            frac = x - np.floor(x)
+            want = (1 - frac) * ftil[iy, j0] + frac * ftil[iy, (j0 + 1) % N]
+            assert abs(out["f"][iy, yx] - want) < 1e-12, (iy, yx)
+    assert multi >= 3 * N                                  # the rule decided on many points
+    assert np.max(res) <= 1e-12
