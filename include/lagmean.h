@@ -235,6 +235,31 @@ typedef enum {
    Synchronous.  For tests. */
 lm_status lm_peek(lm_run* run, int32_t which, double* out, int on_device);
 
+/* Checkpoint and resume, also in the middle of an averaging interval (each
+   interval is independent of the others, section 3, the paragraph after eq.
+   (3.3), but within one interval the partial means, xi and P accumulate from
+   tau on, so resuming mid-interval needs them).  A checkpoint holds the whole
+   state between two steps: every prognostic field as stored (dynamics, the
+   strategy-1, strategy-2 and Eulerian accumulators, xi and P; both words of
+   compensated float32 fields), the step counters and whether an interval is
+   open, behind a header naming the configuration.  lm_restore into a run of
+   the same configuration continues exactly as the saved run would have, bit
+   for bit (the RK4 accumulators are rewritten by the first stage of a step, and
+   the inputs of the next rows passes are transformed from the state by the same
+   kernels the last step's final column pass uses).  The outputs of a closed
+   interval are not part of it.
+     lm_checkpoint_size: bytes a checkpoint of this run takes (host only).
+     lm_save: write the checkpoint to buf (cap bytes, at least the size), a host
+       or device pointer.  LM_E_STATE without a state or inside a batch.
+     lm_restore: take the state from a checkpoint of size bytes.  LM_E_ARG for a
+       buffer that is not a checkpoint, is truncated, or was taken with any other
+       configuration (grid, precision, physics, fields, gathers, driver).
+       LM_E_STATE inside a batch.
+   Synchronous. */
+lm_status lm_checkpoint_size(const lm_run* run, size_t* bytes);
+lm_status lm_save(lm_run* run, void* buf, size_t cap, int on_device);
+lm_status lm_restore(lm_run* run, const void* buf, size_t size, int on_device);
+
 /* Steps taken since lm_set_state and since lm_begin_interval. */
 lm_status lm_counters(lm_run* run, int64_t* steps, int64_t* steps_in_interval);
 

@@ -667,6 +667,127 @@ lm_status lm_peek(lm_run* r, int32_t which, double* out_, int on_device) {
   return LM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// checkpoint layout: this header, then the working-precision state (leading
+// words), its trailing words (float runs) and the float64 state, as stored
+struct CkHeader {
+  char magic[8];
+  int32_t n, precision, interp, mode, mom, gen, fs0, fs1;
+  double f, g, H, dt, nu8, kin[7];
+  int64_t steps, n_tau;
+  int32_t in_interval, reserved;
+  uint64_t bytes_r, bytes_l, bytes_d;
+};
+constexpr char CK_MAGIC[8] = {'L', 'M', 'C', 'K', 'P', 'T', '0', '1'};
+
+CkHeader ck_header(const lm_run* r) {
+  CkHeader h{};
+  memcpy(h.magic, CK_MAGIC, 8);
+  h.n = r->d.N;
+  h.precision = r->fp32 ? LM_FP32_MIXED : LM_FP64;
+  h.interp = r->cfg.interp;
+  h.mode = r->cfg.mode;
+  h.mom = r->ph.mom;
+  h.gen = r->ph.gen;
+  h.fs0 = r->ph.fs0;
+  h.fs1 = r->ph.fs1;
+  h.f = r->ph.f;
+  h.g = r->ph.g;
+  h.H = r->ph.H;
+  h.dt = r->ph.dt;
+  h.nu8 = r->ph.nu8;
+  const double kin[7] = {r->ph.kx, r->ph.ky, r->ph.A, r->ph.omega, r->ph.phase, r->ph.U0, r->ph.V0};
+  memcpy(h.kin, kin, sizeof(kin));
+  h.steps = r->n;
+  h.n_tau = r->n_tau;
+  h.in_interval = r->in_interval ? 1 : 0;
+  const size_t sp = r->d.spec_elems();
+  const size_t cT = r->fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  const int nsf = r->mom ? lm::NSF_R : lm::SF_GMX;
+  h.bytes_r = nsf * sp * cT;
+  h.bytes_l = r->fp32 ? h.bytes_r : 0;
+  h.bytes_d = lm::NSF_D * sp * sizeof(cplx<double>);
+  return h;
+}
+
+size_t ck_size(const CkHeader& h) { return sizeof(CkHeader) + h.bytes_r + h.bytes_l + h.bytes_d; }
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_checkpoint_size(const lm_run* r, size_t* bytes) {
+  if (!r || !bytes) return fail(LM_E_ARG, "null argument");
+  *bytes = ck_size(ck_header(r));
+  return LM_OK;
+}
+
+lm_status lm_save(lm_run* r, void* buf, size_t cap, int on_device) {
+  if (!r || !buf) return fail(LM_E_ARG, "null argument");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  const CkHeader h = ck_header(r);
+  if (cap < ck_size(h)) return fail(LM_E_ARG, "buffer smaller than lm_checkpoint_size");
+  const StreamDrain drain{r->stream};  // every copy has landed before any return
+  const hipMemcpyKind d2x = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  char* out = (char*)buf;
+  if (on_device) HIP_TRY(hipMemcpyAsync(out, &h, sizeof(h), hipMemcpyHostToDevice, r->stream));
+  else memcpy(out, &h, sizeof(h));
+  size_t off = sizeof(h);
+  HIP_TRY(hipMemcpyAsync(out + off, r->slab + r->L.Yr, h.bytes_r, d2x, r->stream));
+  off += h.bytes_r;
+  if (h.bytes_l) HIP_TRY(hipMemcpyAsync(out + off, r->slab + r->L.Yl, h.bytes_l, d2x, r->stream));
+  off += h.bytes_l;
+  HIP_TRY(hipMemcpyAsync(out + off, r->slab + r->L.Yd, h.bytes_d, d2x, r->stream));
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  return LM_OK;
+}
+
+lm_status lm_restore(lm_run* r, const void* buf, size_t size, int on_device) {
+  if (!r || !buf) return fail(LM_E_ARG, "null argument");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
+  const StreamDrain drain{r->stream};
+  CkHeader h{};
+  if (size < sizeof(h)) return fail(LM_E_ARG, "not a checkpoint (too short)");
+  if (on_device) HIP_TRY(hipMemcpy(&h, buf, sizeof(h), hipMemcpyDeviceToHost));
+  else memcpy(&h, buf, sizeof(h));
+  const CkHeader mine = ck_header(r);
+  if (memcmp(h.magic, CK_MAGIC, 8) != 0) return fail(LM_E_ARG, "not a checkpoint of this library");
+  // the configuration must be the run's own, field for field
+  if (h.n != mine.n || h.precision != mine.precision || h.interp != mine.interp || h.mode != mine.mode ||
+      h.mom != mine.mom || h.gen != mine.gen || h.fs0 != mine.fs0 || h.fs1 != mine.fs1 ||
+      memcmp(&h.f, &mine.f, 5 * sizeof(double)) != 0 || memcmp(h.kin, mine.kin, sizeof(h.kin)) != 0 ||
+      h.bytes_r != mine.bytes_r || h.bytes_l != mine.bytes_l || h.bytes_d != mine.bytes_d)
+    return fail(LM_E_ARG, "the checkpoint was taken with another configuration");
+  if (size < ck_size(h)) return fail(LM_E_ARG, "checkpoint truncated");
+  if (h.steps < 0 || h.n_tau < 0 || h.n_tau > h.steps) return fail(LM_E_ARG, "checkpoint counters out of range");
+  const hipMemcpyKind x2d = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const char* in = (const char*)buf;
+  size_t off = sizeof(h);
+  HIP_TRY(hipMemcpyAsync(r->slab + r->L.Yr, in + off, h.bytes_r, x2d, r->stream));
+  off += h.bytes_r;
+  if (h.bytes_l) HIP_TRY(hipMemcpyAsync(r->slab + r->L.Yl, in + off, h.bytes_l, x2d, r->stream));
+  off += h.bytes_l;
+  HIP_TRY(hipMemcpyAsync(r->slab + r->L.Yd, in + off, h.bytes_d, x2d, r->stream));
+  r->n = h.steps;
+  r->n_tau = h.n_tau;
+  r->ys_cur = 0;
+  // the column-pass outputs and stage values of the current state, as the last
+  // step's final column pass left them
+  use_sched(r);
+  LM_DISPATCH_N(r->d.N, lm::launch_prologue, *r);
+  lm_status s;
+  if ((s = check_launch()) != LM_OK) return s;
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  r->has_state = true;
+  r->in_interval = h.in_interval != 0;
+  r->has_mean = r->has_remap = false;
+  return LM_OK;
+}
+
 lm_status lm_counters(lm_run* r, int64_t* steps, int64_t* steps_in_interval) {
   if (!r) return fail(LM_E_ARG, "null run");
   if (steps) *steps = r->n;

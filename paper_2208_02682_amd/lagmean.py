@@ -122,6 +122,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_counters": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "lm_destroy": [P],
         "lm_hip_versions": [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+        "lm_checkpoint_size": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "lm_save": [P, P, ctypes.c_size_t, ctypes.c_int],
+        "lm_restore": [P, P, ctypes.c_size_t, ctypes.c_int],
         "lm_batch_create": [P, ctypes.POINTER(P)],
         "lm_batch_add": [P, P, ctypes.c_int32],
         "lm_batch_remove": [P, P],
@@ -413,6 +416,19 @@ class Run:
         out = np.empty((self.N, self.N))
         _check(self.lib.lm_peek(self.h, PEEK[which], _ptr(out), 0))
         return out
+
+    def save(self) -> np.ndarray:
+        """A checkpoint of the run between steps (lm_save), as bytes on the host."""
+        n = ctypes.c_size_t(0)
+        _check(self.lib.lm_checkpoint_size(self.h, ctypes.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(self.lib.lm_save(self.h, buf.ctypes.data_as(ctypes.c_void_p), n.value, 0))
+        return buf
+
+    def restore(self, blob) -> None:
+        """Continue from a checkpoint taken with lm_save of a run of the same configuration."""
+        b = np.ascontiguousarray(blob, dtype=np.uint8)
+        _check(self.lib.lm_restore(self.h, b.ctypes.data_as(ctypes.c_void_p), b.size, 0))
 
     def counters(self):
         a, b = ctypes.c_int64(0), ctypes.c_int64(0)

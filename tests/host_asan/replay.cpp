@@ -7,7 +7,7 @@
 //   create ID N PREC(0|1) DT INTERP(0|1) FIELDS MODE   lm_create (kin: a plane wave)
 //   set ID                lm_set_state from caller buffers freed right after
 //   begin ID | step ID K | end ID (then lm_read_mean of every output) | state ID
-//   remap ID | peek ID | destroy ID
+//   remap ID | peek ID | destroy ID | save ID | restore ID FROM (a checkpoint of run FROM)
 //   batch                 a new batch (lm_batch_create); one batch at a time
 //   add ID STEPS | remove ID | bstep MAX | bdestroy
 //   expect STATUS         the next call must return STATUS (default LM_OK)
@@ -24,6 +24,7 @@ namespace {
 
 std::map<int, lm_run*> runs;
 std::map<int, int> sizes;
+std::map<int, std::vector<unsigned char>> blobs;  // checkpoints, by the id of the saved run
 lm_batch* batch = nullptr;
 int expect_next = LM_OK;
 long line_no = 0;
@@ -122,6 +123,19 @@ int main(int argc, char** argv) {
         check(lm_read_mean(run(id), LM_FIELD_FIRST, kind, out->data(), 0), "lm_read_mean");
         delete out;
       }
+    } else if (o == "save") {
+      std::sscanf(buf, "%*s %d", &id);
+      size_t n = 0;
+      check(lm_checkpoint_size(run(id), &n), "lm_checkpoint_size");
+      blobs[id].assign(n, 0);
+      check(lm_save(run(id), blobs[id].data(), n, 0), "lm_save");
+    } else if (o == "restore") {
+      int from = 0;
+      std::sscanf(buf, "%*s %d %d", &id, &from);
+      // a copy that dies right after the call
+      std::vector<unsigned char>* b = new std::vector<unsigned char>(blobs[from]);
+      check(lm_restore(run(id), b->data(), b->size(), 0), "lm_restore");
+      delete b;
     } else if (o == "remap") {
       std::sscanf(buf, "%*s %d", &id);
       double res = 0.0;

@@ -48,6 +48,9 @@ def test_batch_of_mixed_runs_is_clean(exe):
     lines += ["batch"] + [f"add {i} {s}" for i, s in zip(range(1, 7), (40, 33, 27, 35, 21, 9))]
     lines += ["bstep 16"] * 3 + [f"remove {i}" for i in range(1, 7)] + ["bdestroy"]
     lines += [f"end {i}" for i in range(1, 7)] + ["remap 3", "state 1", "peek 2", "state 6"]
+    # checkpoints: mid-interval and of a kinematic run, restored into fresh runs
+    lines += ["begin 1", "step 1 3", "save 1", "create 7 256 1 0.0025 0 0 0", "restore 7 1", "step 7 2", "end 7",
+              "save 6", "create 8 64 0 0.01 0 3 1", "restore 8 6", "expect -1", "restore 8 1"]
     out = _clean(exe, "\n".join(lines) + "\n", "batch")
     assert "operations ok" in out
 
