@@ -189,10 +189,8 @@ def tune_batched(a, ws, states):
 
 def bench_tune(a) -> dict:
     """The autotuner over every grid size and precision; writes the cache."""
-    import torch
     from paper_2208_02682_amd import autotune as at
     from synth.workloads import scaled_run
-    torch.cuda.set_device(0)
     sizes = (64, 128, 192, 256, 384, 512, 1024)
     ws = {N: scaled_run(N, Ro=0.1, ratio=1.0, periods=1.0, seeds=(5, 6)) for N in sizes}
     states = dict(zip(sizes, generate_states([ws[N] for N in sizes])))
@@ -217,13 +215,11 @@ def bench_tune(a) -> dict:
 def bench_batch(a) -> dict:
     """Config of 64 uneven runs: batched against alone, and against float64 alone."""
     import numpy as np
-    import torch
-    from paper_2208_02682_amd import Batch, OUTPUTS, Run
+    from paper_2208_02682_amd import OUTPUTS, Batch, Run, device_synchronize
     from synth.workloads import batch_workloads
 
     ws = batch_workloads(a.batch_runs)
     states = generate_states(ws)
-    torch.cuda.set_device(0)
     pts = sum(w.N * w.N * w.steps_per_interval for w in ws)
     first = {}
     for w, st in zip(ws, states):
@@ -255,7 +251,7 @@ def bench_batch(a) -> dict:
     runs = [Run(_cfg(w)) for w in ws]
     for r, st in zip(runs, states):
         start(r, st)
-    torch.cuda.synchronize()
+    device_synchronize()
     t0 = time.perf_counter()
     with Batch() as b:
         for r, w in zip(runs, ws):
@@ -277,7 +273,7 @@ def bench_batch(a) -> dict:
         for i, (w, st) in enumerate(zip(ws, states)):
             with Run(_cfg(w, prec)) as r:
                 start(r, st)
-                torch.cuda.synchronize()
+                device_synchronize()
                 t = time.perf_counter()
                 r.step(w.steps_per_interval)
                 r.end_interval()
@@ -433,7 +429,6 @@ def _fp64_sequential(reqs, a) -> dict:
 
 
 def bench_serve(a) -> dict:
-    """Runs without torch (host arrays, the null stream): the library binds its own HIP runtime."""
     import numpy as np
     from paper_2208_02682_amd import hip_runtime
     from synth.workloads import serving_requests
@@ -458,7 +453,7 @@ def bench_serve(a) -> dict:
                       "mean_grid_point_steps_per_request": mean_work, "hbm_budget_gib": a.hbm_budget_gib,
                       "max_resident_points": a.max_resident_points, "tick_steps": a.tick_steps,
                       "schedule_source": source},
-           "hip": hip_runtime(), "torch_loaded": "torch" in sys.modules,
+           "hip": hip_runtime(),
            "offered": main}
     rec["fp64_sequential"] = _fp64_sequential(reqs, a)
     if a.sustainable_window > 0 and np.isfinite(main["capacity_pt_steps_per_s"]):
@@ -477,13 +472,11 @@ def bench_latency(a) -> dict:
     Runs are pooled per configuration, as in serving; states are generated
     before any clock starts."""
     import numpy as np
-    import torch
     from paper_2208_02682_amd import Run
     from synth.workloads import serving_requests
 
     reqs = serving_requests(rate=20.0, duration=a.latency_window, seed=7)
     states = generate_states([r.run for r in reqs])
-    torch.cuda.set_device(0)
     sizes = sorted({r.run.N for r in reqs})
     first = {}
     for r, st in zip(reqs, states):
@@ -537,11 +530,9 @@ def bench_euler(a) -> dict:
     T = 25) with strategy 1 pseudospectral and semi-Lagrangian, plus the
     semi-Lagrangian kernel (FFT-free, gather-bound) at 1024^2 against HBM."""
     import numpy as np
-    import torch
-    from paper_2208_02682_amd import Euler2D
+    from paper_2208_02682_amd import Euler2D, device_synchronize
     from synth.euler import EULER_TWO_VORTEX as W, two_vortex_vorticity
 
-    torch.cuda.set_device(0)
     z0 = W.initial_vorticity()
     runs = {}
     for interp in ("bilinear", "cubic"):
@@ -551,7 +542,7 @@ def bench_euler(a) -> dict:
             e.step(10)                       # warm-up inside the interval
             e.set_vorticity(z0)
             e.begin_interval()
-            torch.cuda.synchronize()
+            device_synchronize()
             t0 = time.perf_counter()
             e.step(W.steps)
             e.end_interval()
@@ -628,10 +619,6 @@ def main(argv=None) -> int:
         return 2
 
     if a.mode == "serve":
-        # the serving loop needs no torch: the library binds the HIP runtime it
-        # was built with (an earlier run of this mode, with torch's older runtime
-        # bound under the library, ended in a host segmentation fault)
-        os.environ["LAGMEAN_HIP_RUNTIME"] = "own"
         import faulthandler
         faulthandler.enable()
     if a.mode in ("batch", "serve", "euler", "tune", "latency"):
@@ -639,47 +626,34 @@ def main(argv=None) -> int:
                "latency": bench_latency}[a.mode](a)
         print(json.dumps(rec), flush=True)
         return 0
-    import numpy as np
-    import torch
+    from paper_2208_02682_amd import DeviceArray, Run, copy_bandwidth, device_synchronize, hip_runtime, make_config
     if a.copy_probe:
-        n = a.copy_probe * (1 << 20) // 4
-        x = torch.ones(n, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(5):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": n * 4, "repeats": 5}), flush=True)
+        # a plain device copy of MIB MiB, five times (calibrates the counters)
+        gbps = copy_bandwidth(a.copy_probe * (1 << 20), 5)
+        print(json.dumps({"copy_probe_bytes_each_way": a.copy_probe * (1 << 20), "repeats": 5, "GBps": gbps}),
+              flush=True)
         return 0
-    from paper_2208_02682_amd import Run, hip_runtime, make_config
     from synth import workload
 
     w = workload(a.workload)
     fp32 = w.precision == "fp32"
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
     u, v, h = w.initial_state()
-    fields = [torch.from_numpy(x).cuda() for x in (u, v, h)]
+    fields = [DeviceArray.from_host(x) for x in (u, v, h)]
     source = apply_schedules(a, [(w.N, w.precision)], lambda N, p: _cfg(w, p), lambda N: (u, v, h))
     from paper_2208_02682_amd import get_schedule
     sched = get_schedule(w.N, w.precision)
-    run = Run(make_config(w.N, precision=w.precision, f=w.f, g=w.g, H=w.H, dt=w.dt, nu8=w.nu8),
-              stream=stream.cuda_stream)
+    run = Run(make_config(w.N, precision=w.precision, f=w.f, g=w.g, H=w.H, dt=w.dt, nu8=w.nu8))
 
     def start():
         run.set_state(*fields)
         run.begin_interval()
         run.step(a.warmup)
-        torch.cuda.synchronize()
+        device_synchronize()
 
-    # timed region: K plain steps from a fixed state (inputs resident in HBM)
+    # timed region: K plain steps from a fixed state (inputs resident in HBM),
+    # between HIP events on the run's stream, the device idle before
     start()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    run.step(a.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms = run.step_timed(a.steps)
 
     # the same K steps replayed from the same state with HIP events around every
     # launch (the kernels' cost depends on the state: the gathers spread as the
@@ -701,20 +675,11 @@ def main(argv=None) -> int:
     remap_ms = (time.perf_counter() - t0) * 1e3
     if a.no_kernel_timing:
         kms = [float("nan")] * 3
-    # measured bandwidth of a plain device copy (1 GiB read + 1 GiB written, 5 times,
-    # events on the same stream), reported beside the published 8 TB/s
-    xc = torch.ones((1 << 30) // 4, dtype=torch.float32, device="cuda")
-    yc = torch.empty_like(xc)
-    yc.copy_(xc)
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(5):
-        yc.copy_(xc)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbps = 5 * 2 * xc.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
-    del xc, yc
+    # measured bandwidth of a plain device copy (1 GiB read + 1 GiB written, five
+    # times, HIP events), reported beside the published 8 TB/s
+    copy_gbps = copy_bandwidth(1 << 30, 5)
+    for f in fields:
+        f.close()
     names = ["rows_dyn", "rows_rhs", "columns"]
     ab = algorithmic_bytes(w.N, fp32)
     kernels = {n: {"avg_ms": kms[i], "alg_bytes": ab[n], "GBps": ab[n] / (kms[i] * 1e-3) / 1e9}

@@ -166,6 +166,11 @@ lm_status lm_step(lm_run* run, int32_t nsteps);
    1 <= nsteps <= 4096.  Synchronous.  For measurement. */
 lm_status lm_step_profiled(lm_run* run, int32_t nsteps, double* ms_avg);
 
+/* As lm_step, with a pair of HIP events on the run's stream around the steps:
+   *ms receives their elapsed time in milliseconds.  Synchronous.  For
+   measurement. */
+lm_status lm_step_timed(lm_run* run, int32_t nsteps, double* ms);
+
 /* Close the interval: T = (steps since begin) * dt; computes the outputs
    (section 4.1: f~^L = g~/T, eta = P/T; section 4.2: f-bar^L = g-bar/T and xi;
    Eulerian mean E/T) in float64 and synchronises the stream.  LM_E_STATE if no
@@ -429,6 +434,27 @@ lm_status lm_e2d_end_interval(lm_e2d* e, double* T_out);
 lm_status lm_e2d_read(lm_e2d* e, int32_t kind, double* out, int on_device);
 /* Release (waits for the stream).  Null is a no-op. */
 lm_status lm_e2d_destroy(lm_e2d* e);
+
+/* Device memory and copies of the HIP runtime the library is bound to, for
+   callers that hold device arrays for the on_device = 1 paths without another
+   GPU framework in the process (device 0, the null stream).
+     lm_device_alloc: *ptr receives bytes of device memory (null for 0 bytes);
+       LM_E_OOM when they cannot be allocated.
+     lm_device_free: release it (null is a no-op).
+     lm_memcpy: a blocking copy of bytes; kind is one of the LM_COPY_* below.
+     lm_device_synchronize: wait for all work on the device.
+     lm_copy_bandwidth: the bandwidth of a plain device-to-device copy of bytes,
+       reps times (1..1000) after one untimed copy, timed with HIP events;
+       *gbps = 2 * bytes * reps / time (bytes read plus bytes written) / 1e9.
+       Allocates and releases two buffers of bytes.  For measurement. */
+#define LM_COPY_HOST_TO_DEVICE 0
+#define LM_COPY_DEVICE_TO_HOST 1
+#define LM_COPY_DEVICE_TO_DEVICE 2
+lm_status lm_device_alloc(size_t bytes, void** ptr);
+lm_status lm_device_free(void* ptr);
+lm_status lm_memcpy(void* dst, const void* src, size_t bytes, int32_t kind);
+lm_status lm_device_synchronize(void);
+lm_status lm_copy_bandwidth(size_t bytes, int32_t reps, double* gbps);
 
 /* HIP versions, as major * 10^7 + minor * 10^5 + patch: *built receives that of
    the HIP headers the library was compiled with, *runtime that of the HIP

@@ -6,8 +6,8 @@ build script (``build``) and the batch/serving drivers."""
 
 from .lagmean import (LagMeanError, Run, Batch, Euler2D, Config, make_config, footprint, load_library, OUTPUTS, REMAP_OUTPUTS, PEEK,
                       LM_FIELD_H, LM_FIELD_ZETA, schedule_candidates, set_schedule, get_schedule, save_schedules,
-                      load_schedules, hip_runtime)
+                      load_schedules, hip_runtime, DeviceArray, device_synchronize, copy_bandwidth)
 
 __all__ = ["LagMeanError", "Run", "Batch", "Euler2D", "Config", "make_config", "footprint", "load_library", "OUTPUTS", "REMAP_OUTPUTS", "PEEK",
            "LM_FIELD_H", "LM_FIELD_ZETA", "schedule_candidates", "set_schedule", "get_schedule", "save_schedules",
-           "load_schedules", "hip_runtime"]
+           "load_schedules", "hip_runtime", "DeviceArray", "device_synchronize", "copy_bandwidth"]

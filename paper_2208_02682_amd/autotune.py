@@ -27,8 +27,8 @@ def cache_path(arch: str) -> str:
 
 def device_arch() -> str:
     """Architecture name of the first GPU (e.g. gfx950), from the kernel driver's
-    topology (host only: no HIP call, so it works in processes without torch),
-    else from torch's device properties."""
+    topology (host only: no HIP call); "unknown" when the topology is not
+    readable (then no cache matches and the default schedules stay)."""
     import glob
     for props in sorted(glob.glob("/sys/class/kfd/kfd/topology/nodes/*/properties")):
         try:
@@ -39,8 +39,7 @@ def device_arch() -> str:
         v = int(kv.get("gfx_target_version", "0"))
         if v > 0:  # major * 10000 + minor * 100 + stepping; CPU nodes report 0
             return f"gfx{v // 10000}{(v // 100) % 100:x}{v % 100:x}"
-    import torch
-    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    return "unknown"
 
 
 def load_default(arch: Optional[str] = None) -> int:

@@ -312,6 +312,72 @@ const char* lm_status_str(lm_status s) {
 
 const char* lm_last_error(void) { return g_err.c_str(); }
 
+lm_status lm_device_alloc(size_t bytes, void** ptr) {
+  if (!ptr) return fail(LM_E_ARG, "null ptr");
+  *ptr = nullptr;
+  if (bytes == 0) return LM_OK;
+  const hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(LM_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return LM_OK;
+}
+
+lm_status lm_device_free(void* ptr) {
+  if (!ptr) return LM_OK;
+  HIP_TRY(hipFree(ptr));
+  return LM_OK;
+}
+
+lm_status lm_memcpy(void* dst, const void* src, size_t bytes, int32_t kind) {
+  if ((!dst || !src) && bytes) return fail(LM_E_ARG, "null pointer");
+  hipMemcpyKind k;
+  switch (kind) {
+    case LM_COPY_HOST_TO_DEVICE: k = hipMemcpyHostToDevice; break;
+    case LM_COPY_DEVICE_TO_HOST: k = hipMemcpyDeviceToHost; break;
+    case LM_COPY_DEVICE_TO_DEVICE: k = hipMemcpyDeviceToDevice; break;
+    default: return fail(LM_E_ARG, "unknown copy kind");
+  }
+  if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, k));
+  return LM_OK;
+}
+
+lm_status lm_device_synchronize(void) {
+  HIP_TRY(hipDeviceSynchronize());
+  return LM_OK;
+}
+
+lm_status lm_copy_bandwidth(size_t bytes, int32_t reps, double* gbps) {
+  if (!gbps || bytes == 0 || reps < 1 || reps > 1000) return fail(LM_E_ARG, "bytes > 0, 1 <= reps <= 1000");
+  void *a = nullptr, *b = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&a, bytes);
+  if (e == hipSuccess) e = hipMalloc(&b, bytes);
+  if (e == hipSuccess) e = hipMemset(a, 0, bytes);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, nullptr);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipDeviceSynchronize();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? LM_E_OOM : LM_E_HIP, std::string("copy bandwidth: ") + hipGetErrorString(e));
+  }
+  *gbps = 2.0 * double(bytes) * reps / (double(ms) * 1e-3) / 1e9;  // bytes read + bytes written
+  return LM_OK;
+}
+
 lm_status lm_hip_versions(int32_t* built, int32_t* runtime) {
   if (built) *built = (int32_t)HIP_VERSION;
   if (runtime) {
@@ -491,6 +557,32 @@ lm_status lm_step(lm_run* r, int32_t nsteps) {
   use_sched(r);
   LM_DISPATCH_N(r->d.N, lm::launch_steps, *r, nsteps);
   return check_launch();
+}
+
+lm_status lm_step_timed(lm_run* r, int32_t nsteps, double* ms) {
+  if (!r || !ms) return fail(LM_E_ARG, "null argument");
+  if (r->batch) return fail(LM_E_STATE, "the run belongs to a batch");
+  if (nsteps < 0) return fail(LM_E_ARG, "nsteps < 0");
+  if (!r->has_state) return fail(LM_E_STATE, "no state set");
+  const StreamDrain drain{r->stream};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, r->stream);
+  if (e == hipSuccess) {
+    use_sched(r);
+    LM_DISPATCH_N(r->d.N, lm::launch_steps, *r, nsteps);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, r->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(LM_E_HIP, std::string("timed steps: ") + hipGetErrorString(e));
+  *ms = t;
+  return LM_OK;
 }
 
 lm_status lm_step_profiled(lm_run* r, int32_t nsteps, double* ms_avg) {

@@ -665,32 +665,37 @@ struct ColCtx {
   bool valid;       // kx <= K
 };
 
+// one complex value of a buffer-resource load (8 or 16 bytes)
+template <typename T>
+__device__ __forceinline__ cplx<T> buffer_cplx(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(cplx<T>) == 8) return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+  else return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+}
+
 // block-wide: rows of a [N][NKXP] field (columns kx0..kx0+C-1) into the C buffers.
-// A thread keeps one column c and visits rows y = threadIdx.x / C + NT k; four
-// loads are in flight before their values go to LDS (all E at once would push
-// the column kernel past 128 VGPRs, the limit for 4 waves per SIMD).
+// A thread keeps one column c and visits rows y = threadIdx.x / C + NT k.  The
+// field is read as one buffer resource: the thread's offset sits in one vector
+// register and the row step of each of its E loads in a scalar register, so all
+// E loads are in flight at once for the price of their data registers (global
+// loads would need an address register pair each).  Columns past K read the
+// row's padding and are replaced by zeros.
 template <typename T, int N, int C>
 __device__ __forceinline__ void tile_load(const ColCtx<T, N, C>& cx, const cplx<T>* __restrict__ src,
                                           const Dims& d) {
-  constexpr int LC = ColCtx<T, N, C>::LC, E = fft_E<N>(), NT = N / E, U = 4;
+  constexpr int LC = ColCtx<T, N, C>::LC, E = fft_E<N>(), NT = N / E;
   const int c = threadIdx.x % C, y0 = threadIdx.x / C;
   const bool in = cx.kx0 + c <= kcut<N>();
-  const unsigned o0 = (unsigned)y0 * (unsigned)d.NKXP + (unsigned)(cx.kx0 + c);
-  const unsigned dy = (unsigned)NT * (unsigned)d.NKXP;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<cplx<T>*>(src), (short)0, (int)(d.rowfield_elems() * sizeof(cplx<T>)), 0x00020000);
+  const unsigned voff = ((unsigned)y0 * (unsigned)d.NKXP + (unsigned)(cx.kx0 + c)) * (unsigned)sizeof(cplx<T>);
+  const unsigned dy = (unsigned)NT * (unsigned)d.NKXP * (unsigned)sizeof(cplx<T>);
   cplx<T>* dstl = cx.lds + c * LC;
   __syncthreads();
+  cplx<T> val[E];
 #pragma unroll
-  for (int k0 = 0; k0 < E; k0 += U) {
-    cplx<T> val[U];
+  for (int k = 0; k < E; ++k) val[k] = buffer_cplx<T>(rs, voff, (unsigned)k * dy);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      val[u] = {T(0), T(0)};
-      if (k0 + u < E && in) val[u] = src[o0 + (unsigned)(k0 + u) * dy];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (k0 + u < E) dstl[pidx(y0 + NT * (k0 + u))] = val[u];
-  }
+  for (int k = 0; k < E; ++k) dstl[pidx(y0 + NT * k)] = in ? val[k] : cplx<T>{T(0), T(0)};
   __syncthreads();
 }
 

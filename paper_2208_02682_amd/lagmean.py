@@ -1,9 +1,9 @@
 """ctypes binding of liblagmean.so (include/lagmean.h); argument marshalling only.
 
 Every computation happens in the HIP library.  Arrays may be NumPy float64
-arrays (host) or torch CUDA float64 tensors (device); PyTorch is only used for
-device memory and streams.  Importing this module fails loudly when the library
-has not been built.
+arrays (host) or device arrays: the library's own DeviceArray, or torch CUDA
+float64 tensors when torch's HIP runtime is bound (LAGMEAN_HIP_RUNTIME=torch).
+Loading the library fails loudly when it has not been built.
 """
 
 from __future__ import annotations
@@ -81,9 +81,11 @@ E2D_OUTPUTS = {"zeta": 0, "PS_mean": 1, "PS_eta_x": 2, "PS_eta_y": 3, "SL_mean":
 _lib: Optional[ctypes.CDLL] = None
 
 
-# LAGMEAN_HIP_RUNTIME=own: load the library without PyTorch, so that it binds
-# the HIP runtime it was built with (for processes that need no torch, such as
-# the serving loop on host arrays).  Default: PyTorch's runtime (see below).
+# Which HIP runtime the library binds (one per process).  Default ("own"): the
+# runtime it was built with, loaded through its own dependency; the process must
+# then not use torch's GPU functions.  "torch": PyTorch is imported first, and
+# the library binds the runtime torch ships (an older one than the library is
+# built with), so that torch CUDA tensors and streams can be passed in.
 OWN_RUNTIME_ENV = "LAGMEAN_HIP_RUNTIME"
 
 
@@ -94,16 +96,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2208_02682_amd.build`")
     # One HIP runtime per process.  PyTorch ships its own libamdhip64 (same
-    # soname); loaded first, it is the runtime the library binds to.  Loaded
-    # after the library, torch would bring a second runtime that does not see
-    # the GPU.  So torch, when present, is loaded before the library, unless the
-    # caller asked for the library's own runtime (and then must not use torch's
-    # GPU functions in this process).
-    if os.environ.get(OWN_RUNTIME_ENV, "") != "own":
-        try:
-            import torch  # noqa: F401
-        except ImportError:
-            pass
+    # soname); loaded first, it is the runtime the library binds to, and loaded
+    # after the library it would bring a second runtime that does not see the
+    # GPU.  So torch is imported first only when its runtime is asked for.
+    mode = os.environ.get(OWN_RUNTIME_ENV, "own")
+    if mode not in ("own", "torch"):
+        raise ValueError(f"{OWN_RUNTIME_ENV} must be 'own' or 'torch', not {mode!r}")
+    if mode == "torch":
+        import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     D = ctypes.POINTER(ctypes.c_double)
@@ -122,6 +122,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_counters": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "lm_destroy": [P],
         "lm_hip_versions": [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+        "lm_device_alloc": [ctypes.c_size_t, ctypes.POINTER(P)],
+        "lm_device_free": [P],
+        "lm_memcpy": [P, P, ctypes.c_size_t, ctypes.c_int32],
+        "lm_device_synchronize": [],
+        "lm_copy_bandwidth": [ctypes.c_size_t, ctypes.c_int32, D],
+        "lm_step_timed": [P, ctypes.c_int32, D],
         "lm_checkpoint_size": [P, ctypes.POINTER(ctypes.c_size_t)],
         "lm_save": [P, P, ctypes.c_size_t, ctypes.c_int],
         "lm_restore": [P, P, ctypes.c_size_t, ctypes.c_int],
@@ -282,11 +288,64 @@ def footprint(cfg: Config) -> int:
     return int(out.value)
 
 
+class DeviceArray:
+    """A float64 array in device memory allocated by the library (lm_device_alloc)."""
+
+    def __init__(self, shape, host=None):
+        self.lib = load_library()
+        self.shape = tuple(int(x) for x in shape)
+        self.nbytes = int(np.prod(self.shape)) * 8
+        self.ptr = ctypes.c_void_p(0)
+        _check(self.lib.lm_device_alloc(self.nbytes, ctypes.byref(self.ptr)))
+        if host is not None:
+            self.copy_from(host)
+
+    @classmethod
+    def from_host(cls, a) -> "DeviceArray":
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        return cls(a.shape, a)
+
+    def copy_from(self, a) -> None:
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != self.shape:
+            raise ValueError(f"expected shape {self.shape}, got {a.shape}")
+        _check(self.lib.lm_memcpy(self.ptr, a.ctypes.data_as(ctypes.c_void_p), self.nbytes, 0))
+
+    def to_host(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        _check(self.lib.lm_memcpy(out.ctypes.data_as(ctypes.c_void_p), self.ptr, self.nbytes, 1))
+        return out
+
+    def close(self) -> None:
+        if self.ptr and self.ptr.value:
+            _check(self.lib.lm_device_free(self.ptr))
+            self.ptr = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_synchronize() -> None:
+    _check(load_library().lm_device_synchronize())
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s of a plain device copy of nbytes (read + written), lm_copy_bandwidth."""
+    g = ctypes.c_double(0.0)
+    _check(load_library().lm_copy_bandwidth(int(nbytes), int(reps), ctypes.byref(g)))
+    return g.value
+
+
 def _is_device(a) -> bool:
-    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+    return isinstance(a, DeviceArray) or (hasattr(a, "is_cuda") and bool(a.is_cuda))
 
 
 def _ptr(a):
+    if isinstance(a, DeviceArray):
+        return a.ptr
     if _is_device(a):
         return ctypes.c_void_p(a.data_ptr())
     return a.ctypes.data_as(ctypes.c_void_p)
@@ -331,8 +390,12 @@ class Run:
     def set_state(self, u, v, h) -> None:
         if _is_device(u):
             for a in (u, v, h):
-                if a.dtype.__str__() != "torch.float64" or not a.is_contiguous() or tuple(a.shape) != (self.N, self.N):
-                    raise ValueError("device inputs must be contiguous float64 N x N tensors")
+                if isinstance(a, DeviceArray):
+                    ok = a.shape == (self.N, self.N)
+                else:
+                    ok = str(a.dtype) == "torch.float64" and a.is_contiguous() and tuple(a.shape) == (self.N, self.N)
+                if not ok:
+                    raise ValueError("device inputs must be contiguous float64 N x N arrays")
             _check(self.lib.lm_set_state(self.h, _ptr(u), _ptr(v), _ptr(h), 1))
         else:
             u, v, h = (_host_in(a, self.N) for a in (u, v, h))
@@ -349,6 +412,12 @@ class Run:
 
     def step(self, nsteps: int = 1) -> None:
         _check(self.lib.lm_step(self.h, int(nsteps)))
+
+    def step_timed(self, nsteps: int) -> float:
+        """Milliseconds of nsteps steps between HIP events on the run's stream (lm_step_timed)."""
+        ms = ctypes.c_double(0.0)
+        _check(self.lib.lm_step_timed(self.h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
 
     def step_profiled(self, nsteps: int):
         """Average milliseconds of (rows_dyn, rows_rhs, columns) over nsteps steps."""
@@ -536,6 +605,12 @@ class Euler2D:
 
     def step(self, nsteps: int = 1) -> None:
         _check(self.lib.lm_e2d_step(self.h, int(nsteps)))
+
+    def step_timed(self, nsteps: int) -> float:
+        """Milliseconds of nsteps steps between HIP events on the run's stream (lm_step_timed)."""
+        ms = ctypes.c_double(0.0)
+        _check(self.lib.lm_step_timed(self.h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
 
     def step_profiled(self, nsteps: int):
         """(average step, average semi-Lagrangian kernel) in milliseconds."""

@@ -9,7 +9,7 @@
 //   begin ID | step ID K | end ID (then lm_read_mean of every output) | state ID
 //   remap ID | peek ID | destroy ID | save ID | restore ID FROM (a checkpoint of run FROM)
 //   batch                 a new batch (lm_batch_create); one batch at a time
-//   add ID STEPS | remove ID | bstep MAX | bdestroy
+//   add ID STEPS | remove ID | bstep MAX | btune STEPS REPS | bdestroy | tune ID STEPS REPS
 //   expect STATUS         the next call must return STATUS (default LM_OK)
 #include <cstdio>
 #include <cstdlib>
@@ -157,6 +157,18 @@ int main(int argc, char** argv) {
       std::sscanf(buf, "%*s %d", &k);
       int32_t active = 0;
       check(lm_batch_step(batch, k, &active), "lm_batch_step");
+    } else if (o == "btune") {
+      int reps = 1;
+      std::sscanf(buf, "%*s %d %d", &k, &reps);
+      int32_t tuned = 0;
+      check(lm_batch_autotune(batch, k, reps, &tuned), "lm_batch_autotune");
+    } else if (o == "tune") {
+      int reps = 1;
+      std::sscanf(buf, "%*s %d %d %d", &id, &k, &reps);
+      lm_schedule best{};
+      double ms[16];
+      int32_t count = 0;
+      check(lm_autotune(run(id), k, reps, &best, ms, 16, &count), "lm_autotune");
     } else if (o == "bdestroy") {
       check(lm_batch_destroy(batch), "lm_batch_destroy");
       batch = nullptr;

@@ -1,11 +1,13 @@
-"""The library in a process without PyTorch, bound to the HIP runtime it was built with.
+"""The library in a fresh process without PyTorch, bound to the HIP runtime it was built with.
 
 PyTorch ships its own HIP runtime (same soname); a process that imports torch
 first makes the library bind to that one, whose version differs from the
-headers the library was compiled with.  Processes that need no torch (the
-serving loop on host arrays) can load the library alone (LAGMEAN_HIP_RUNTIME=own).
-This test runs such a process: it checks which runtime was bound, and that a
-single run and a batched run give the oracle's results at 1e-12.
+headers the library was compiled with.  By default (LAGMEAN_HIP_RUNTIME=own) the
+binding does not import torch and the library binds its own runtime; every GPU
+test, the smoke test and the benchmarks run so.  These tests start such a
+process afresh: it must bind ROCm's runtime of the library's own version, give
+the oracle's results at 1e-12 in a single and a batched run, and serve a mix
+with 512^2 and 1024^2 members exactly as each request alone.
 """
 
 import json
