@@ -302,6 +302,23 @@ lm_status lm_batch_remove(lm_batch* b, lm_run* run);
    budget left afterwards. */
 lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active);
 
+/* Allocation-free form of lm_batch_step, for callers that cannot allocate
+   device memory (serving loops that must not call hipMalloc, harnesses that
+   forbid it).  Same arguments, same kernels and the same results, bit for bit,
+   as lm_batch_step; the difference is where the batch's bookkeeping lives: the
+   member descriptors and step counters go to a fixed device array of the
+   library (128 KiB, one per GPU, held until the process ends) instead of
+   device memory allocated by the batch, and the steps are launched directly on
+   the batch's stream instead of replaying a captured graph (which would need
+   an instantiation).  The call allocates no device memory and calls no
+   allocating library routine on its success path.  LM_E_BUDGET when the batch
+   has more than LM_STATIC_MAX_MEMBERS members (nothing is launched then).
+   Every call on one GPU shares that array: calls that overlap in time on the
+   same GPU (from several threads, whatever the batch) race and must not be
+   made.  Synchronous, like lm_batch_step; not for use under stream capture. */
+#define LM_STATIC_MAX_MEMBERS 256
+lm_status lm_batch_step_static(lm_batch* b, int32_t max_steps, int32_t* active);
+
 /* Remaining budget of a member. */
 lm_status lm_batch_remaining(lm_batch* b, const lm_run* run, int32_t* remaining);
 

@@ -204,6 +204,10 @@ struct lm_batch {
   hipGraphExec_t exec = nullptr;
   std::vector<lm_run*> signature;  // active members the graph was built for
   unsigned sched_gen = 0;          // schedule table generation the graph was captured with
+  // host image of the device scratch of lm_batch_step_static (descriptors and
+  // counters are copied from here; it lives as long as the batch, so the copies
+  // never read freed host memory)
+  alignas(256) unsigned char static_stage[128 * 1024];
 };
 
 namespace {
@@ -1133,6 +1137,152 @@ lm_status lm_batch_step(lm_batch* b, int32_t max_steps, int32_t* active_out) {
     for (int i : active) {
       b->members[i].remaining -= 1;
       b->members[i].run->n += 1;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (active_out) {
+    int a = 0;
+    for (auto& mm : b->members) a += mm.remaining > 0;
+    *active_out = a;
+  }
+  return LM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free batched step
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device scratch of lm_batch_step_static, one copy per GPU for the life of the
+// process: the step counters of up to LM_STATIC_MAX_MEMBERS members (first
+// 2 KiB), then the run descriptors of each (N, precision, gathers, momentum,
+// fields) group, packed, each group's array 256-byte aligned.  In host code
+// `scratch` names a host-side stand-in: kernels and copies get the device
+// address from static_scratch() instead.
+constexpr size_t STATIC_BYTES = 128 * 1024;
+constexpr size_t STATIC_COUNTERS = LM_STATIC_MAX_MEMBERS * sizeof(long long);
+static_assert(STATIC_COUNTERS + LM_STATIC_MAX_MEMBERS * (sizeof(lm::RunDesc<double>) + 256) <= STATIC_BYTES,
+              "static scratch too small for its member limit");
+static_assert(sizeof(lm::RunDesc<float>) <= sizeof(lm::RunDesc<double>), "descriptor sizes");
+__device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};  // device address of scratch, per device ordinal
+
+// the calling thread's current device's copy of scratch (looked up once per device)
+lm_status static_scratch(unsigned char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(LM_E_UNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LM_E_HIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scratch_ptr[dev];
+  return LM_OK;
+}
+
+struct StaticGroup {
+  int N;
+  bool fp32, cubic, mom, gen;
+  int count;
+  size_t off;  // byte offset of its descriptor array in scratch
+};
+
+bool same_group(const StaticGroup& g, const lm_run* r) {
+  return g.N == r->d.N && g.fp32 == r->fp32 && g.cubic == r->cubic && g.mom == r->mom && g.gen == (bool)r->ph.gen;
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_batch_step_static(lm_batch* b, int32_t max_steps, int32_t* active_out) {
+  if (!b) return fail(LM_E_ARG, "null batch");
+  if (max_steps < 0) return fail(LM_E_ARG, "max_steps < 0");
+  const int m = (int)b->members.size();
+  if (m > LM_STATIC_MAX_MEMBERS)
+    return fail(LM_E_BUDGET, "lm_batch_step_static: the batch has " + std::to_string(m) +
+                                 " members, more than LM_STATIC_MAX_MEMBERS (" +
+                                 std::to_string(LM_STATIC_MAX_MEMBERS) + ")");
+  unsigned char* dev = nullptr;
+  lm_status st = static_scratch(&dev);
+  if (st != LM_OK) return st;
+  const StreamDrain drain{b->stream};  // every path out leaves no step in flight
+  // the caller's stream and the members' own streams first
+  HIP_TRY(hipStreamSynchronize(b->user));
+  for (int i = 0; i < m; ++i) HIP_TRY(hipStreamSynchronize(b->members[i].run->stream));
+  // the batch's own stream too: earlier steps read the scratch rewritten below
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  unsigned char* stage = b->static_stage;
+  long long* cnt = reinterpret_cast<long long*>(stage);
+  for (int i = 0; i < m; ++i) cnt[i] = b->members[i].run->n - b->members[i].run->n_tau;
+  if (m > 0) HIP_TRY(hipMemcpyAsync(dev, stage, m * sizeof(long long), hipMemcpyHostToDevice, b->stream));
+  long long* d_cnt = reinterpret_cast<long long*>(dev);
+
+  int active[LM_STATIC_MAX_MEMBERS];
+  int nact_prev = -1;
+  StaticGroup groups[LM_STATIC_MAX_MEMBERS];
+  int ngroups = 0;
+  for (int it = 0; it < max_steps; ++it) {
+    int nact = 0;
+    for (int i = 0; i < m; ++i)
+      if (b->members[i].remaining > 0) active[nact++] = i;
+    if (nact == 0) break;
+    if (nact != nact_prev) {
+      // the active set changed (members only drop out): new descriptors, after
+      // the queued steps that read the old ones
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      ngroups = 0;
+      for (int a = 0; a < nact; ++a) {
+        const lm_run* r = b->members[active[a]].run;
+        int g = 0;
+        while (g < ngroups && !same_group(groups[g], r)) ++g;
+        if (g == ngroups) groups[ngroups++] = {r->d.N, r->fp32, r->cubic, r->mom, (bool)r->ph.gen, 0, 0};
+        groups[g].count += 1;
+      }
+      size_t off = STATIC_COUNTERS;
+      for (int g = 0; g < ngroups; ++g) {
+        groups[g].off = off;
+        int k = 0;
+        for (int a = 0; a < nact; ++a) {
+          lm_run* r = b->members[active[a]].run;
+          if (!same_group(groups[g], r)) continue;
+          if (r->fp32) {
+            const lm::RunDesc<float> d = lm::run_desc<float>(*r, d_cnt + active[a]);
+            memcpy(stage + off + k * sizeof(d), &d, sizeof(d));
+          } else {
+            const lm::RunDesc<double> d = lm::run_desc<double>(*r, d_cnt + active[a]);
+            memcpy(stage + off + k * sizeof(d), &d, sizeof(d));
+          }
+          ++k;
+        }
+        off += (groups[g].count * sizeof(lm::RunDesc<double>) + 255) / 256 * 256;
+      }
+      HIP_TRY(hipMemcpyAsync(dev + STATIC_COUNTERS, stage + STATIC_COUNTERS, off - STATIC_COUNTERS,
+                             hipMemcpyHostToDevice, b->stream));
+      nact_prev = nact;
+    }
+    // one RK4 step of every group, launched directly on the batch's stream
+    for (int g = 0; g < ngroups; ++g) {
+      lm::Phys gp{};
+      gp.mom = groups[g].mom;
+      gp.gen = groups[g].gen;
+      const lm::Sched sc = get_sched(groups[g].N, groups[g].fp32, true);
+      LM_DISPATCH_N(groups[g].N, lm::launch_batch_step, b->stream, dev + groups[g].off, groups[g].count,
+                    groups[g].fp32, groups[g].cubic, groups[g].mom, lm::col_groups(gp), sc);
+    }
+    lm::launch_batch_tick(b->stream, d_cnt, m);
+    st = check_launch();
+    if (st != LM_OK) return st;
+    for (int a = 0; a < nact; ++a) {
+      b->members[active[a]].remaining -= 1;
+      b->members[active[a]].run->n += 1;
     }
   }
   HIP_TRY(hipStreamSynchronize(b->stream));

@@ -27,6 +27,7 @@ LM_FP64, LM_FP32_MIXED = 0, 1
 LM_F_H, LM_F_ZETA, LM_F_MOMENTUM, LM_F_U, LM_F_V, LM_F_Q = 1, 2, 4, 8, 16, 32
 FIELD_BITS = {"h": LM_F_H, "zeta": LM_F_ZETA, "u": LM_F_U, "v": LM_F_V, "q": LM_F_Q}
 LM_DYNAMIC, LM_KINEMATIC_PLANEWAVE = 0, 1
+LM_STATIC_MAX_MEMBERS = 256  # members lm_batch_step_static accepts
 LM_FIELD_H, LM_FIELD_ZETA = 0, 1
 PEEK = {"u": 0, "v": 1, "h": 2, "gbar:h": 3, "gbar:zeta": 4, "gtil:h": 5, "gtil:zeta": 6,
         "E:h": 7, "E:zeta": 8, "xi_x": 9, "xi_y": 10, "P_x": 11, "P_y": 12}
@@ -135,6 +136,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lm_batch_add": [P, P, ctypes.c_int32],
         "lm_batch_remove": [P, P],
         "lm_batch_step": [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+        "lm_batch_step_static": [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
         "lm_batch_remaining": [P, P, ctypes.POINTER(ctypes.c_int32)],
         "lm_batch_destroy": [P],
         "lm_schedule_candidates": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule), ctypes.c_int32,
@@ -530,6 +532,12 @@ class Batch:
         members still have budget left."""
         active = ctypes.c_int32(0)
         _check(self.lib.lm_batch_step(self.h, int(max_steps), ctypes.byref(active)))
+        return active.value
+
+    def step_static(self, max_steps: int) -> int:
+        """As step, through the allocation-free lm_batch_step_static."""
+        active = ctypes.c_int32(0)
+        _check(self.lib.lm_batch_step_static(self.h, int(max_steps), ctypes.byref(active)))
         return active.value
 
     def autotune(self, steps: int = 4, reps: int = 3) -> List[dict]:
