@@ -10,6 +10,7 @@
 
 #include "lagmean.h"
 #include "launch.hpp"
+#include "twiddles.hpp"
 
 using lm::cplx;
 
@@ -227,11 +228,7 @@ lm_status lm_e2d_create(const lm_e2d_config* cfg, void* hip_stream, lm_e2d** out
     (void)hipGetLastError();
     return fail(LM_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(err));
   }
-  std::vector<cplx<double>> tw(n);
-  for (int m = 0; m < n; ++m) {
-    const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
-    tw[m] = {(double)cosl(a), (double)sinl(a)};
-  }
+  const std::vector<cplx<double>> tw = lm::stage_twiddles<double>(n);
   err = hipMemcpy(e->v.slab + e->v.L.tw64, tw.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice);
   if (err != hipSuccess) {
     (void)hipFree(e->v.slab);

@@ -12,9 +12,12 @@
 // Stockham autosort formulation (decimation in time): at a stage with radix R
 // applied after sub-transforms of length Ns, butterfly j (0 <= j < N/R) reads
 // in[j + r N/R], multiplies by w_{Ns R}^{r (j mod Ns)}, does an R-point DFT and
-// writes out[(j / Ns) Ns R + (j mod Ns) + r Ns].  Twiddles come from one table
-// tw[m] = exp(-2 pi i m / N) (host-computed in long double), index
-// m = r (j mod Ns) N / (Ns R) < N.
+// writes out[(j / Ns) Ns R + (j mod Ns) + r Ns], with twiddle w_N^m,
+// m = r (j mod Ns) N / (Ns R).  The twiddles (host-computed in long double) are
+// stored stage by stage: the block of a stage holds entry (r - 1) Ns + k =
+// exp(-2 pi i r k / (Ns R)) for r = 1..R-1, k < Ns, so the lanes of a wavefront
+// (consecutive j) read consecutive entries of one block, a few cache lines per
+// load instead of one line per lane.
 #pragma once
 
 #include <type_traits>
@@ -222,22 +225,47 @@ __device__ __forceinline__ void dft(cplx<T>* v) {
 // plans: N = E * R2 * R3 * R4 with E values per lane; the first stage is a
 // radix-E DFT in registers, the later radices divide E
 // ---------------------------------------------------------------------------
+struct Radices {
+  int R2, R3, R4;
+};
+__host__ __device__ constexpr Radices plan_of(int n, int e) {
+  if (e == 16) {
+    switch (n) {
+      case 16: return {1, 1, 1};
+      case 32: return {2, 1, 1};
+      case 64: return {4, 1, 1};
+      case 128: return {8, 1, 1};
+      case 256: return {16, 1, 1};
+      case 512: return {16, 2, 1};
+      case 1024: return {16, 4, 1};
+      default: break;
+    }
+  } else if (e == 12) {
+    if (n == 192) return {4, 4, 1};
+    if (n == 384) return {4, 4, 2};
+  }
+  return {0, 0, 0};
+}
 template <int N, int E>
-struct Plan;
-template <> struct Plan<16, 16>   { static constexpr int R2 = 1,  R3 = 1, R4 = 1; };
-template <> struct Plan<32, 16>   { static constexpr int R2 = 2,  R3 = 1, R4 = 1; };
-template <> struct Plan<64, 16>   { static constexpr int R2 = 4,  R3 = 1, R4 = 1; };
-template <> struct Plan<128, 16>  { static constexpr int R2 = 8,  R3 = 1, R4 = 1; };
-template <> struct Plan<256, 16>  { static constexpr int R2 = 16, R3 = 1, R4 = 1; };
-template <> struct Plan<512, 16>  { static constexpr int R2 = 16, R3 = 2, R4 = 1; };
-template <> struct Plan<1024, 16> { static constexpr int R2 = 16, R3 = 4, R4 = 1; };
-template <> struct Plan<64, 8>    { static constexpr int R2 = 8,  R3 = 1, R4 = 1; };
-template <> struct Plan<128, 8>   { static constexpr int R2 = 8,  R3 = 2, R4 = 1; };
-template <> struct Plan<256, 8>   { static constexpr int R2 = 8,  R3 = 4, R4 = 1; };
-template <> struct Plan<512, 8>   { static constexpr int R2 = 8,  R3 = 8, R4 = 1; };
-template <> struct Plan<1024, 8>  { static constexpr int R2 = 8,  R3 = 8, R4 = 2; };
-template <> struct Plan<192, 12>  { static constexpr int R2 = 4,  R3 = 4, R4 = 1; };
-template <> struct Plan<384, 12>  { static constexpr int R2 = 4,  R3 = 4, R4 = 2; };
+struct Plan {
+  static constexpr Radices p = plan_of(N, E);
+  static_assert(p.R2 > 0 && E * p.R2 * p.R3 * p.R4 == N, "no FFT plan for this length");
+  static constexpr int R2 = p.R2, R3 = p.R3, R4 = p.R4;
+};
+
+// offset of stage s (0, 1, 2: the stages of radix R2, R3, R4) in the stage-by-
+// stage twiddle table, and the table's length (at most n for every plan)
+__host__ __device__ constexpr int tw_offset(int n, int e, int s) {
+  const Radices p = plan_of(n, e);
+  const int R[3] = {p.R2, p.R3, p.R4};
+  int off = 0, ns = e;
+  for (int i = 0; i < s; ++i) {
+    if (R[i] > 1) off += (R[i] - 1) * ns;
+    ns *= R[i];
+  }
+  return off;
+}
+__host__ __device__ constexpr int tw_len(int n, int e) { return tw_offset(n, e, 3); }
 
 // values per lane of the column and row passes: 16 for powers of two (a
 // 1024-point transform stays inside one wavefront, no workgroup barriers;
@@ -262,7 +290,8 @@ template <typename T>
 using gptr = const __attribute__((address_space(1))) cplx<T>*;
 
 // one Stockham stage of radix R after sub-transforms of length Ns (Ns > 1),
-// reading and writing the group's LDS buffer; TW is the twiddle pointer type
+// reading and writing the group's LDS buffer; tw: the stage's twiddle block,
+// TW its pointer type
 template <typename T, int N, int E, int DIR, int Ns, int R, typename TW>
 __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, TW tw) {
   constexpr int NT = N / E;
@@ -282,8 +311,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int t, TW tw) {
     const int k = j % Ns;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      const int m = r * k * (N / (Ns * R));
-      const cplx<T> w = {tw[m].x, tw[m].y};
+      const cplx<T> w = {tw[(r - 1) * Ns + k].x, tw[(r - 1) * Ns + k].y};
       v[b * R + r] = (DIR < 0) ? cmul(v[b * R + r], w) : cmulc(v[b * R + r], w);
     }
     dft<R, DIR>(&v[b * R]);
@@ -341,8 +369,7 @@ __device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw, cpl
   const int k = t % 16;
 #pragma unroll
   for (int r = 1; r < 16; ++r) {
-    const int m = r * k * (N / 256);
-    const cplx<T> w = {tw[m].x, tw[m].y};
+    const cplx<T> w = {tw[(r - 1) * 16 + k].x, tw[(r - 1) * 16 + k].y};
     x[r] = (DIR < 0) ? cmul(x[r], w) : cmulc(x[r], w);
   }
   dft<16, DIR>(x);
@@ -360,6 +387,7 @@ __device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw, cpl
   }
   // the buffer is rewritten below: every lane's reads above come first
   xsync<NT>();
+  const TW twB = tw + 15 * 16;  // the radix-G stage's twiddle block
   // radix-G stage after sub-transforms of length 256: butterfly b of lane t
   // combines entries j + 256 r, j = t + NT b
 #pragma unroll
@@ -367,8 +395,7 @@ __device__ __forceinline__ void stages_16_then_G(cplx<T>* buf, int t, TW tw, cpl
     const int j = t + NT * b;
 #pragma unroll
     for (int r = 1; r < G; ++r) {
-      const int m = r * j;
-      const cplx<T> w = {tw[m].x, tw[m].y};
+      const cplx<T> w = {twB[(r - 1) * 256 + j].x, twB[(r - 1) * 256 + j].y};
       x[b * G + r] = (DIR < 0) ? cmul(x[b * G + r], w) : cmulc(x[b * G + r], w);
     }
     dft<G, DIR>(&x[b * G]);
@@ -414,9 +441,11 @@ __device__ __forceinline__ void fft(cplx<T> (&v)[E], cplx<T>* buf, int t, const 
     stages_16_then_G<T, N, E, DIR, KEEP>(buf, t, ptw, v);
   } else {
     static_assert(!KEEP, "only the lane-swap plans keep their output in registers");
-    if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, ptw);
-    if constexpr (PL::R3 > 1) stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, ptw);
-    if constexpr (PL::R4 > 1) stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, ptw);
+    if constexpr (PL::R2 > 1) stockham_stage<T, N, E, DIR, E, PL::R2>(buf, t, ptw + tw_offset(N, E, 0));
+    if constexpr (PL::R3 > 1)
+      stockham_stage<T, N, E, DIR, E * PL::R2, PL::R3>(buf, t, ptw + tw_offset(N, E, 1));
+    if constexpr (PL::R4 > 1)
+      stockham_stage<T, N, E, DIR, E * PL::R2 * PL::R3, PL::R4>(buf, t, ptw + tw_offset(N, E, 2));
   }
 }
 

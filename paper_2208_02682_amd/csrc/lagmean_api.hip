@@ -16,6 +16,7 @@
 
 #include "lagmean.h"
 #include "launch.hpp"
+#include "twiddles.hpp"
 
 using lm::cplx;
 
@@ -437,15 +438,10 @@ lm_status lm_create(const lm_config* cfg, void* hip_stream, lm_run** out) {
     delete r;
     return fail(LM_E_HIP, std::string("stream creation: ") + hipGetErrorString(e));
   }
-  // twiddles exp(-2 pi i m / N), long double on the host
+  // twiddles exp(-2 pi i m / N) in the transforms' stage-by-stage layout
   const int N = r->d.N;
-  std::vector<cplx<double>> tw(N);
-  std::vector<cplx<float>> twf(N);
-  for (int m = 0; m < N; ++m) {
-    const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)N;
-    tw[m] = {(double)cosl(a), (double)sinl(a)};
-    twf[m] = {(float)cosl(a), (float)sinl(a)};
-  }
+  const std::vector<cplx<double>> tw = lm::stage_twiddles<double>(N);
+  const std::vector<cplx<float>> twf = lm::stage_twiddles<float>(N);
   e = hipMemcpy(r->slab + r->L.tw64, tw.data(), N * sizeof(cplx<double>), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = r->fp32 ? hipMemcpy(r->slab + r->L.twT, twf.data(), N * sizeof(cplx<float>), hipMemcpyHostToDevice)
