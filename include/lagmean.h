@@ -342,8 +342,8 @@ lm_status lm_batch_destroy(lm_batch* b);
  *              two streams (the run's and one of its own): the dynamics rows
  *              pass and the column groups of u, v, h on one, the mean
  *              right-hand-side rows pass and the mean column groups on the
- *              other, so that the mean column groups of a stage overlap the
- *              next stage's dynamics rows pass.  Ordering with the caller is
+ *              other, so that the column groups of u, v, h overlap the mean
+ *              right-hand-side passes of the same stage.  Ordering with the caller is
  *              unchanged: lm_step's work still ends on the run's stream.
  *              Batched launches (captured graphs) take 1.
  * Two process-wide schedule tables, one entry per (n, precision) each: one for

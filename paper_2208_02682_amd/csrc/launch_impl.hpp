@@ -82,15 +82,17 @@ void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
 }
 
 // Two-stream form of the steps.  Per stage the dependencies are
-//   rows_dyn(i)  <- the dynamics column groups of stage i-1 (their outputs) and
-//                   rows_rhs(i-1) (it reads the physical fields rows_dyn rewrites),
+//   rows_dyn(i)  <- the dynamics column groups of stage i-1 (their outputs),
+//                   rows_rhs(i-1) (it reads the physical fields rows_dyn rewrites)
+//                   and the mean column groups of stage i-1 (the Eulerian
+//                   accumulators among them read the stage values that the
+//                   dynamics groups of stage i overwrite),
 //   rows_rhs(i)  <- rows_dyn(i) and the mean column groups of stage i-1,
 //   dynamics column groups(i) <- rows_dyn(i),  mean column groups(i) <- rows_rhs(i),
 // and no pass writes what a pass it may overlap with reads.  The auxiliary
 // stream carries rows_dyn and the dynamics groups, the run's stream rows_rhs
-// and the mean groups, so the mean groups of stage i overlap rows_dyn of stage
-// i+1 and the dynamics groups overlap rows_rhs.  Same kernels, same arguments,
-// same results as the one-stream form.
+// and the mean groups, so the dynamics groups overlap rows_rhs and the mean
+// groups.  Same kernels, same arguments, same results as the one-stream form.
 template <typename T, int N>
 hipError_t launch_steps_2s(RunView& r, int nsteps) {
   const StepPtrs<T> P = step_ptrs<T>(r);
@@ -102,7 +104,10 @@ hipError_t launch_steps_2s(RunView& r, int nsteps) {
   for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
     for (int stage = 0; stage < 4 && e == hipSuccess; ++stage) {
       const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
-      if (s + stage > 0) e = hipStreamWaitEvent(r.aux, rhs, 0);  // rows_rhs of the previous stage
+      // the previous stage's run-stream work: rows_rhs reads the physical
+      // fields rows_dyn rewrites, and the mean groups read the stage values the
+      // next dynamics groups overwrite
+      if (s + stage > 0) e = hipStreamWaitEvent(r.aux, rhs, 0);
       if (e != hipSuccess) break;
       hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.aux, P, r.d, r.ph,
                          r.sched.remap);
@@ -111,8 +116,8 @@ hipError_t launch_steps_2s(RunView& r, int nsteps) {
       if (e == hipSuccess) e = hipStreamWaitEvent(r.stream, dyn, 0);
       if (e != hipSuccess) break;
       launch_rows_rhs<T, N>(r, P, sval);  // on the run's stream
-      e = hipEventRecord(rhs, r.stream);
       launch_columns_part<T, N>(r, stage, nd, nm, r.stream);
+      e = hipEventRecord(rhs, r.stream);
       r.ys_cur ^= 1;
     }
     r.n += 1;

@@ -619,40 +619,57 @@ __device__ __forceinline__ void comp_add(float& hi, float& lo, float d) {
   hi = h2;
 }
 
-// classical RK4: returns the next stage input (the new state after stage 3).
-// Float state is compensated: Yp holds the leading word and Lp the trailing
-// one, so the state itself carries about 48 significant bits and the rounding
-// of the state at every step no longer accumulates over a long run.  Stage
-// inputs, right-hand sides and the accumulator Ap stay float (their rounding
-// enters once per step, scaled by dt).  Float64 state ignores Lp.
+// Classical RK4 on one coefficient, in registers: y the state, lo its trailing
+// word (compensated float state), a the accumulator of k1 + 2 k2 + 2 k3; k the
+// stage's right-hand side.  Returns the next stage input (the new state after
+// stage 3) and updates a (stages 0-2) or y and lo (stage 3), which the caller
+// stores.  Float state is compensated: y holds the leading word and lo the
+// trailing one, so the state itself carries about 48 significant bits and the
+// rounding of the state at every step no longer accumulates over a long run.
+// Stage inputs, right-hand sides and the accumulator stay float (their rounding
+// enters once per step, scaled by dt).  Float64 state ignores lo.
 template <typename TS>
-__device__ __forceinline__ cplx<TS> rk4(int stage, cplx<TS>* __restrict__ Yp, cplx<TS>* __restrict__ Lp,
-                                        cplx<TS>* __restrict__ Ap, cplx<TS> k, double dt) {
-  const cplx<TS> y = *Yp;
+__device__ __forceinline__ cplx<TS> rk4v(int stage, cplx<TS>& y, cplx<TS>& lo, cplx<TS>& a, cplx<TS> k,
+                                         double dt) {
   if (stage == 0) {
-    *Ap = k;
+    a = k;
     const TS c = TS(0.5 * dt);
     return {y.x + c * k.x, y.y + c * k.y};
   } else if (stage == 1 || stage == 2) {
-    const cplx<TS> a = *Ap;
-    *Ap = {a.x + TS(2) * k.x, a.y + TS(2) * k.y};
+    a = {a.x + TS(2) * k.x, a.y + TS(2) * k.y};
     const TS c = TS(stage == 1 ? 0.5 * dt : dt);
     return {y.x + c * k.x, y.y + c * k.y};
   } else {
-    const cplx<TS> a = *Ap;
     const TS c = TS(dt / 6.0);
     if constexpr (std::is_same<TS, float>::value) {
-      cplx<TS> hi = y, lo = *Lp;
-      comp_add(hi.x, lo.x, c * (a.x + k.x));
-      comp_add(hi.y, lo.y, c * (a.y + k.y));
-      *Yp = hi;
-      *Lp = lo;
-      return hi;
+      comp_add(y.x, lo.x, c * (a.x + k.x));
+      comp_add(y.y, lo.y, c * (a.y + k.y));
     } else {
-      const cplx<TS> yn = {y.x + c * (a.x + k.x), y.y + c * (a.y + k.y)};
-      *Yp = yn;
-      return yn;
+      y = {y.x + c * (a.x + k.x), y.y + c * (a.y + k.y)};
     }
+    return y;
+  }
+}
+
+// the words rk4v reads (y always, a from stage 1, lo at stage 3 for float) and
+// writes back (a at stages 0-2, y and lo at stage 3)
+template <typename TS>
+__device__ __forceinline__ void rk4_load(int stage, const cplx<TS>* Yp, const cplx<TS>* Lp, const cplx<TS>* Ap,
+                                         cplx<TS>& y, cplx<TS>& lo, cplx<TS>& a) {
+  y = *Yp;
+  if (stage >= 1) a = *Ap;
+  if constexpr (std::is_same<TS, float>::value) {
+    if (stage == 3) lo = *Lp;
+  }
+}
+template <typename TS>
+__device__ __forceinline__ void rk4_store(int stage, cplx<TS>* Yp, cplx<TS>* Lp, cplx<TS>* Ap, const cplx<TS>& y,
+                                          const cplx<TS>& lo, const cplx<TS>& a) {
+  if (stage <= 2) {
+    *Ap = a;
+  } else {
+    *Yp = y;
+    if constexpr (std::is_same<TS, float>::value) *Lp = lo;
   }
 }
 
@@ -843,70 +860,136 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
   const T fT = T(ph.f), gT = T(ph.g), HT = T(ph.H);
 
   cplx<TS> S[E];
+  if (stage < 0 || (DYN && ph.kin)) {
+    // prologue (the current state's transforms) or a prescribed flow
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int k = cx.t + NT * r;
-    int ky;
-    bool in = true;
-    if (k <= K) ky = k;
-    else if (k >= N - K) ky = k - N;
-    else { ky = 0; in = false; }
-    S[r] = {TS(0), TS(0)};
-    if (!(in && cx.valid)) continue;
-    const size_t j = col + (size_t)(ky + K);
-    const T kxT = T(cx.kx), kyT = T(ky);
-    if constexpr (G == CG_H) {
-      // Eulerian accumulators of (eta, zeta) from the stage values: dE_eta/dt = eta
-      // (h less H at k = 0), dE_zeta/dt = i kx v - i ky u (other averaged fields:
-      // groups CG_EF0 / CG_EF1)
-      if (stage >= 0 && !ph.gen) {
-        const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
-        cplx<T> eta = h;
-        if (cx.kx == 0 && ky == 0) eta.x -= HT;
-        rk4<T>(stage, P.Yr + SF_EH * sp + j, P.Yl + SF_EH * sp + j, P.Ar + SF_EH * sp + j, eta, ph.dt);
-        const cplx<T> zeta = {-kxT * v.y + kyT * u.y, kxT * v.x - kyT * u.x};
-        rk4<T>(stage, P.Yr + SF_EZ * sp + j, P.Yl + SF_EZ * sp + j, P.Ar + SF_EZ * sp + j, zeta, ph.dt);
+    for (int r = 0; r < E; ++r) {
+      const int k = cx.t + NT * r;
+      int ky;
+      bool in = true;
+      if (k <= K) ky = k;
+      else if (k >= N - K) ky = k - N;
+      else { ky = 0; in = false; }
+      S[r] = {TS(0), TS(0)};
+      if (!(in && cx.valid)) continue;
+      const size_t j = col + (size_t)(ky + K);
+      if constexpr (DYN) {
+        if (ph.kin) {
+          // the next stage input is the prescribed flow at t_next
+          const cplx<double> c = kin_coef<G>(cx.kx, ky, t_next, ph);
+          S[r] = {TS(c.x), TS(c.y)};
+          Ys_out[(G - CG_U) * sp + j] = S[r];
+          continue;
+        }
       }
-    }
-    if constexpr (DYN) {
-      if (ph.kin) {
-        // prescribed flow: the next stage input is the flow at t_next
-        const cplx<double> c = kin_coef<G>(cx.kx, ky, t_next, ph);
-        S[r] = {TS(c.x), TS(c.y)};
-        Ys_out[(G - CG_U) * sp + j] = S[r];
-        continue;
-      }
-    }
-    if (stage < 0) {
       S[r] = Y[j];
       if constexpr (DYN) Ys_out[(G - CG_U) * sp + j] = S[r];
-      continue;
     }
-    const double k2 = double(cx.kx) * cx.kx + double(ky) * ky;
-    const T hv = T(ph.nu8 * (k2 * k2) * (k2 * k2));
-    cplx<T> R;
-    if constexpr (G == CG_U) {
-      // zeta v + f v - i kx (g h + K) - nu8 |k|^8 u
-      const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
-      const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
-      R = {r0[r].x + fT * v.x + kxT * B.y - hv * u.x, r0[r].y + fT * v.y - kxT * B.x - hv * u.y};
-    } else if constexpr (G == CG_V) {
-      // -zeta u - f u - i ky (g h + K) - nu8 |k|^8 v
-      const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
-      const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
-      R = {-r0[r].x - fT * u.x + kyT * B.y - hv * v.x, -r0[r].y - fT * u.y - kyT * B.x - hv * v.y};
-    } else if constexpr (G == CG_H) {
-      // -i kx (H u + F(eta u)) - i ky (H v + F(eta v)) - nu8 |k|^8 h
-      const cplx<T> u = Ys_in[0 * sp + j], v = Ys_in[1 * sp + j], h = Ys_in[2 * sp + j];
-      const cplx<T> fx = {HT * u.x + r0[r].x, HT * u.y + r0[r].y};
-      const cplx<T> fy = {HT * v.x + r1[r].x, HT * v.y + r1[r].y};
-      R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
-    } else {
-      R = r0[r];
+  } else {
+    // RK4 stage.  The coefficients are taken in batches of RB: every load of a
+    // batch (stage values, state, accumulator) is issued before its first
+    // store, so the batch's loads are in flight together (stores to the state
+    // could alias later loads as far as the compiler knows, which would
+    // otherwise serialise the coefficients).
+    // The Eulerian accumulators of the default averaged fields ride along with
+    // the g-tilde groups (E_eta with g-tilde_h, E_zeta with g-tilde_zeta): they
+    // read the stage values but need no transform, and the dynamics groups
+    // already move the most data.  (Other averaged fields: groups CG_EF0/EF1.)
+    constexpr bool EULA = (G == CG_GTH), EULB = (G == CG_GTZ);
+    const bool eul = (EULA || EULB) && !ph.gen;
+    constexpr int RB = (DYN || DBL || EULA || EULB) ? 2 : 4;
+    static_assert(E % RB == 0, "coefficient batches");
+#pragma unroll
+    for (int r0i = 0; r0i < E; r0i += RB) {
+      bool ok[RB];
+      int kyv[RB];
+      cplx<T> su[RB], sv[RB], sh[RB];
+      cplx<TS> y[RB], lo[RB], a[RB];
+      cplx<T> ey[RB], el[RB], ea[RB];  // Eulerian accumulator
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int k = cx.t + NT * (r0i + q);
+        int ky;
+        bool in = true;
+        if (k <= K) ky = k;
+        else if (k >= N - K) ky = k - N;
+        else { ky = 0; in = false; }
+        ok[q] = in && cx.valid;
+        kyv[q] = ky;
+        if (!ok[q]) continue;
+        const size_t j = col + (size_t)(ky + K);
+        if constexpr (DYN) {
+          su[q] = Ys_in[0 * sp + j];
+          sv[q] = Ys_in[1 * sp + j];
+          sh[q] = Ys_in[2 * sp + j];
+        }
+        rk4_load<TS>(stage, Y + j, YL + j, A + j, y[q], lo[q], a[q]);
+        if constexpr (EULA || EULB) {
+          if (eul) {
+            constexpr int se = EULA ? SF_EH : SF_EZ;
+            if constexpr (EULA) {
+              sh[q] = Ys_in[2 * sp + j];
+            } else {
+              su[q] = Ys_in[0 * sp + j];
+              sv[q] = Ys_in[1 * sp + j];
+            }
+            rk4_load<T>(stage, P.Yr + se * sp + j, P.Yl + se * sp + j, P.Ar + se * sp + j, ey[q], el[q], ea[q]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int r = r0i + q;
+        S[r] = {TS(0), TS(0)};
+        if (!ok[q]) continue;
+        const int ky = kyv[q];
+        const size_t j = col + (size_t)(ky + K);
+        const T kxT = T(cx.kx), kyT = T(ky);
+        if constexpr (EULA || EULB) {
+          // Eulerian accumulators from the stage values: dE_eta/dt = eta (h less H
+          // at k = 0), dE_zeta/dt = i kx v - i ky u
+          if (eul) {
+            constexpr int se = EULA ? SF_EH : SF_EZ;
+            cplx<T> f;
+            if constexpr (EULA) {
+              f = sh[q];
+              if (cx.kx == 0 && ky == 0) f.x -= HT;
+            } else {
+              f = {-kxT * sv[q].y + kyT * su[q].y, kxT * sv[q].x - kyT * su[q].x};
+            }
+            rk4v<T>(stage, ey[q], el[q], ea[q], f, ph.dt);
+            rk4_store<T>(stage, P.Yr + se * sp + j, P.Yl + se * sp + j, P.Ar + se * sp + j, ey[q], el[q], ea[q]);
+          }
+        }
+        const double k2 = double(cx.kx) * cx.kx + double(ky) * ky;
+        const T hv = T(ph.nu8 * (k2 * k2) * (k2 * k2));
+        cplx<T> R;
+        if constexpr (G == CG_U) {
+          // zeta v + f v - i kx (g h + K) - nu8 |k|^8 u
+          const cplx<T> u = su[q], v = sv[q], h = sh[q];
+          const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
+          R = {r0[r].x + fT * v.x + kxT * B.y - hv * u.x, r0[r].y + fT * v.y - kxT * B.x - hv * u.y};
+        } else if constexpr (G == CG_V) {
+          // -zeta u - f u - i ky (g h + K) - nu8 |k|^8 v
+          const cplx<T> u = su[q], v = sv[q], h = sh[q];
+          const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
+          R = {-r0[r].x - fT * u.x + kyT * B.y - hv * v.x, -r0[r].y - fT * u.y - kyT * B.x - hv * v.y};
+        } else if constexpr (G == CG_H) {
+          // -i kx (H u + F(eta u)) - i ky (H v + F(eta v)) - nu8 |k|^8 h
+          const cplx<T> u = su[q], v = sv[q], h = sh[q];
+          const cplx<T> fx = {HT * u.x + r0[r].x, HT * u.y + r0[r].y};
+          const cplx<T> fy = {HT * v.x + r1[r].x, HT * v.y + r1[r].y};
+          R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
+        } else {
+          R = r0[r];
+          (void)hv;
+        }
+        const cplx<TS> Rk = {TS(R.x), TS(R.y)};
+        S[r] = rk4v<TS>(stage, y[q], lo[q], a[q], Rk, ph.dt);
+        rk4_store<TS>(stage, Y + j, YL + j, A + j, y[q], lo[q], a[q]);
+        if constexpr (DYN) Ys_out[(G - CG_U) * sp + j] = S[r];
+      }
     }
-    const cplx<TS> Rk = {TS(R.x), TS(R.y)};
-    S[r] = rk4<TS>(stage, Y + j, YL + j, A + j, Rk, ph.dt);
-    if constexpr (DYN) Ys_out[(G - CG_U) * sp + j] = S[r];
   }
 
   // inverse column transforms of the next stage input
@@ -954,12 +1037,12 @@ __device__ __forceinline__ void columns_body(const StepPtrs<T>& P, const Dims& d
 #undef LM_CG
 }
 
-// float32: ask for 4 resident waves per SIMD (at most 128 VGPRs) where the kernel
-// reaches that without spilling; at 512, and in the batched kernel at 1024, the
-// same request spills, and float64 is out of its reach
+// float32: ask for 4 resident waves per SIMD (at most 128 registers), which
+// every size reaches without spilling more than a few words; float64 is out of
+// its reach
 template <typename T, int N, bool BATCHED>
 __host__ __device__ constexpr int col_waves() {
-  return (sizeof(T) == 4 && N != 512 && !(BATCHED && N == 1024)) ? 4 : 1;
+  return sizeof(T) == 4 ? 4 : 1;
 }
 
 // W: column tile width (col_tile<N, W>)
