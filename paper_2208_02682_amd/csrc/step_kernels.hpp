@@ -729,11 +729,11 @@ __device__ __forceinline__ void tile_store(const ColCtx<T, N, C>& cx, cplx<T>* _
   __syncthreads();
 }
 
-// forward column transform of one row-spectrum field; returns the masked,
-// 1/N^2-normalised right-hand-side values at k = t + NT r
+// forward column transform of one row-spectrum field; the spectrum is left in
+// the wave's buffer (natural order), unnormalised
 template <typename T, int N, int C>
-__device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const cplx<T>* src, const Dims& d,
-                                               const cplx<T>* __restrict__ tw, cplx<T> (&out)[fft_E<N>()]) {
+__device__ __forceinline__ void column_forward_lds(const ColCtx<T, N, C>& cx, const cplx<T>* src, const Dims& d,
+                                                   const cplx<T>* __restrict__ tw) {
   constexpr int E = fft_E<N>(), NT = N / E;
   tile_load<T, N, C>(cx, src, d);
   cplx<T> v[E];
@@ -741,12 +741,27 @@ __device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const 
   for (int r = 0; r < E; ++r) v[r] = cx.buf[pidx(cx.t + NT * r)];
   xsync<NT>();
   fft<T, N, fft_E<N>(), -1>(v, cx.buf, cx.t, tw);
+}
+
+// the masked, 1/N^2-normalised right-hand-side value at k = t + NT r from the
+// spectrum column_forward_lds left in the buffer
+template <typename T, int N, int C>
+__device__ __forceinline__ cplx<T> column_value(const ColCtx<T, N, C>& cx, int r) {
+  constexpr int NT = N / fft_E<N>();
   const T inv = T(1.0 / (double(N) * double(N)));
+  const cplx<T> q = cx.buf[pidx(cx.t + NT * r)];
+  return {q.x * inv, q.y * inv};
+}
+
+// forward column transform of one row-spectrum field; returns the masked,
+// 1/N^2-normalised right-hand-side values at k = t + NT r
+template <typename T, int N, int C>
+__device__ __forceinline__ void column_forward(const ColCtx<T, N, C>& cx, const cplx<T>* src, const Dims& d,
+                                               const cplx<T>* __restrict__ tw, cplx<T> (&out)[fft_E<N>()]) {
+  constexpr int E = fft_E<N>();
+  column_forward_lds<T, N, C>(cx, src, d, tw);
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const cplx<T> q = cx.buf[pidx(cx.t + NT * r)];
-    out[r] = {q.x * inv, q.y * inv};
-  }
+  for (int r = 0; r < E; ++r) out[r] = column_value<T, N, C>(cx, r);
 }
 
 // inverse column transform of values S at k = t + NT r (already zero outside
@@ -833,11 +848,13 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
                    : (G == CG_PX) ? RS_PX : (G == CG_PY) ? RS_PY : (G == CG_GMX) ? RS_GMX
                    : (G == CG_GMY) ? RS_GMY : (G == CG_EF0) ? RS_F0 : RS_F1;
   constexpr int F1 = (G == CG_U || G == CG_V) ? RS_K : RS_HV;
-  cplx<T> r0[E], r1[E];
+  // the first input's values in registers; the second one's (dynamics groups)
+  // stay in the wave's buffer until the stage update reads them
+  cplx<T> r0[E];
   // a kinematic run has no dynamics right-hand sides
   if (stage >= 0 && !(DYN && ph.kin)) {
     column_forward<T, N, C>(cx, P.RS + F0 * rf, d, P.tw, r0);
-    if constexpr (NF == 2) column_forward<T, N, C>(cx, P.RS + F1 * rf, d, P.tw, r1);
+    if constexpr (NF == 2) column_forward_lds<T, N, C>(cx, P.RS + F1 * rf, d, P.tw);
   }
 
   // state of this group
@@ -897,7 +914,8 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     // already move the most data.  (Other averaged fields: groups CG_EF0/EF1.)
     constexpr bool EULA = (G == CG_GTH), EULB = (G == CG_GTZ);
     const bool eul = (EULA || EULB) && !ph.gen;
-    constexpr int RB = (DYN || DBL || EULA || EULB) ? 2 : 4;
+    constexpr int RB0 = (DBL || DYN || EULA || EULB) ? 4 : 8;
+    constexpr int RB = (E % RB0 == 0) ? RB0 : 4;
     static_assert(E % RB == 0, "coefficient batches");
 #pragma unroll
     for (int r0i = 0; r0i < E; r0i += RB) {
@@ -967,18 +985,21 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         if constexpr (G == CG_U) {
           // zeta v + f v - i kx (g h + K) - nu8 |k|^8 u
           const cplx<T> u = su[q], v = sv[q], h = sh[q];
-          const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
+          const cplx<T> r1 = column_value<T, N, C>(cx, r);
+          const cplx<T> B = {gT * h.x + r1.x, gT * h.y + r1.y};
           R = {r0[r].x + fT * v.x + kxT * B.y - hv * u.x, r0[r].y + fT * v.y - kxT * B.x - hv * u.y};
         } else if constexpr (G == CG_V) {
           // -zeta u - f u - i ky (g h + K) - nu8 |k|^8 v
           const cplx<T> u = su[q], v = sv[q], h = sh[q];
-          const cplx<T> B = {gT * h.x + r1[r].x, gT * h.y + r1[r].y};
+          const cplx<T> r1 = column_value<T, N, C>(cx, r);
+          const cplx<T> B = {gT * h.x + r1.x, gT * h.y + r1.y};
           R = {-r0[r].x - fT * u.x + kyT * B.y - hv * v.x, -r0[r].y - fT * u.y - kyT * B.x - hv * v.y};
         } else if constexpr (G == CG_H) {
           // -i kx (H u + F(eta u)) - i ky (H v + F(eta v)) - nu8 |k|^8 h
           const cplx<T> u = su[q], v = sv[q], h = sh[q];
           const cplx<T> fx = {HT * u.x + r0[r].x, HT * u.y + r0[r].y};
-          const cplx<T> fy = {HT * v.x + r1[r].x, HT * v.y + r1[r].y};
+          const cplx<T> r1 = column_value<T, N, C>(cx, r);
+          const cplx<T> fy = {HT * v.x + r1.x, HT * v.y + r1.y};
           R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
         } else {
           R = r0[r];
