@@ -109,7 +109,7 @@ hipError_t launch_steps_2s(RunView& r, int nsteps) {
       // next dynamics groups overwrite
       if (s + stage > 0) e = hipStreamWaitEvent(r.aux, rhs, 0);
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.aux, P, r.d, r.ph,
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(rows_dyn_tasks<T>(r.ph)), dim3(64 * ROW_WAVES), 0, r.aux, P, r.d, r.ph,
                          r.sched.remap);
       e = hipEventRecord(dyn, r.aux);
       launch_columns_part<T, N>(r, stage, 0, nd, r.aux);
@@ -140,7 +140,7 @@ void launch_steps_t(RunView& r, int nsteps) {
     for (int stage = 0; stage < 4; ++stage) {
       // time since the interval start, from integers
       const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(rows_dyn_tasks<T>(r.ph)), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
                          r.ph, r.sched.remap);
       launch_rows_rhs<T, N>(r, P, sval);
       launch_columns_t<T, N>(r, stage);
@@ -175,7 +175,7 @@ hipError_t launch_steps_profiled_t(RunView& r, int nsteps, double* ms) {
       // start marker absorbs the work done at kernel boundaries, so each
       // interval covers one kernel's execution only
       (void)hipEventRecord(ev[e++], r.stream);
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(1), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(rows_dyn_tasks<T>(r.ph)), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
                          r.ph, r.sched.remap);
       (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
@@ -214,7 +214,7 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool
   const Dims d = Dims::make(N);
   const int rm = sc.remap;
   for (int stage = 0; stage < 4; ++stage) {
-    dim3 g1 = row_grid<N>(1);
+    dim3 g1 = row_grid<N>(rows_dyn_ntask<T>());  // members with a prescribed flow end tasks 1, 2 at once
     g1.z = nruns;
     hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, dim3(64 * ROW_WAVES), 0, st, desc, rm);
     dim3 g2 = row_grid<N>(NRT);

@@ -280,9 +280,16 @@ __device__ __forceinline__ T field_value(int fs, const cplx<T>& uv, const cplx<T
   }
 }
 
+// One row of the dynamics rows pass, as ntask tasks.  Each task inverse-
+// transforms the row's (u, v) and (eta, zeta) and forms its products: task 0
+// stores the physical fields for the gathers, then zeta v, zeta u; task 1
+// K, eta u; task 2 eta v (one task: all of them).  Float runs take three short
+// waves per row instead of one long one, which keeps the SIMDs busy (one row
+// per wave leaves a single wave on each SIMD); the products are the same.  A
+// prescribed flow runs task 0 only.
 template <typename T, int N>
 __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& d, const Phys& ph, int rowblock,
-                                              cplx<T>* lds) {
+                                              int task, int ntask, cplx<T>* lds) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
   const int grp = row_group<NT>(), t = threadIdx.x % NT;
@@ -291,6 +298,7 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
   const size_t rf = d.rowfield_elems();
   const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
   constexpr int K = kcut<N>();
+  if (task > 0 && ph.kin) return;  // prescribed flow: only the physical fields
 
   cplx<T> uv[E], hz[E];
   load_pair<T, N, false, false>(uv, ICr + IC_U * rf, ICr + IC_V * rf, t);
@@ -317,43 +325,57 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
   }
   inverse_row<T, N>(hz, buf, t, P.tw);
 
-  // u, v and the two averaged fields, interleaved for the gathers
-  P4<T>* out = P.uvhz + (size_t)y * N;
   cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
   cplx<T> z[E];
-  if (ph.fs0 == FS_ETA && ph.fs1 == FS_ZETA) {
+  if (task == 0) {
+    // u, v and the two averaged fields, interleaved for the gathers
+    P4<T>* out = P.uvhz + (size_t)y * N;
+    if (ph.fs0 == FS_ETA && ph.fs1 == FS_ZETA) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, hz[e].x, hz[e].y};
-  } else {
+      for (int e = 0; e < E; ++e) out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, hz[e].x, hz[e].y};
+    } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      z[e] = {field_value<T>(ph.fs0, uv[e], hz[e], ph), field_value<T>(ph.fs1, uv[e], hz[e], ph)};
-      out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, z[e].x, z[e].y};
+      for (int e = 0; e < E; ++e) {
+        z[e] = {field_value<T>(ph.fs0, uv[e], hz[e], ph), field_value<T>(ph.fs1, uv[e], hz[e], ph)};
+        out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, z[e].x, z[e].y};
+      }
+      // their spectra, for the Eulerian means
+      if (ph.gen) forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_F0 * rf, RSr + RS_F1 * rf);
     }
-    // their spectra, for the Eulerian means
-    if (ph.gen) forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_F0 * rf, RSr + RS_F1 * rf);
+    if (ph.kin) return;  // prescribed flow: no dynamics
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
+    forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
+    if (ntask > 1) return;
   }
-  if (ph.kin) return;  // prescribed flow: no dynamics
+  if (task == 1 || ntask == 1) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      z[e] = {T(0.5) * (uv[e].x * uv[e].x + uv[e].y * uv[e].y), hz[e].x * uv[e].x};  // K, eta u
+    forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
+    if (ntask > 1) return;
+  }
+  {
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[e] = {hz[e].x * uv[e].y, T(0)};  // eta v
+    forward_row<T, N, false, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
+  }
+}
 
-
-#pragma unroll
-  for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
-  forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
-#pragma unroll
-  for (int e = 0; e < E; ++e)
-    z[e] = {T(0.5) * (uv[e].x * uv[e].x + uv[e].y * uv[e].y), hz[e].x * uv[e].x};  // K, eta u
-  forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
-#pragma unroll
-  for (int e = 0; e < E; ++e) z[e] = {hz[e].x * uv[e].y, T(0)};  // eta v
-  forward_row<T, N, false, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
+// float: three resident waves per SIMD (at most 168 registers), one per task
+// of a row
+template <typename T>
+__host__ __device__ constexpr int dyn_waves() {
+  return sizeof(T) == 4 ? 3 : 1;
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn(StepPtrs<T> P, Dims d, Phys ph, int remap) {
+__global__ void __launch_bounds__(64 * ROW_WAVES, (dyn_waves<T>())) k_rows_dyn(StepPtrs<T> P, Dims d, Phys ph,
+                                                                              int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
-  int rowblock, unused, z;
-  xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
-  rows_dyn_body<T, N>(P, d, ph, rowblock, lds);
+  int rowblock, task, z;
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);  // grid = (row blocks, tasks)
+  rows_dyn_body<T, N>(P, d, ph, rowblock, task, (int)gridDim.y, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -1083,11 +1105,12 @@ __global__ void __launch_bounds__((col_threads<N, W>()), (col_waves<T, N, false>
 // --------------------------------------------------------------------------
 
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_dyn_b(const RunDesc<T>* __restrict__ runs, int remap) {
+__global__ void __launch_bounds__(64 * ROW_WAVES, (dyn_waves<T>())) k_rows_dyn_b(const RunDesc<T>* __restrict__ runs,
+                                                                                int remap) {
   __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
-  int rowblock, unused, z;
-  xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
-  rows_dyn_body<T, N>(runs[z].P, Dims::make(N), runs[z].ph, rowblock, lds);
+  int rowblock, task, z;
+  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);
+  rows_dyn_body<T, N>(runs[z].P, Dims::make(N), runs[z].ph, rowblock, task, (int)gridDim.y, lds);
 }
 
 template <typename T, int N, bool CUB>
