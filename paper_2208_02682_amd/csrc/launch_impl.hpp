@@ -18,6 +18,15 @@ template <int N>
 dim3 row_grid(int tasks) {
   return dim3(N / RowGeo<N>::RPB, tasks);
 }
+// the dynamics rows pass (its block shape depends on the precision)
+template <typename T, int N>
+dim3 dyn_grid() {
+  return dim3(N / DynGeo<T, N>::RPB);
+}
+template <typename T, int N>
+dim3 dyn_block() {
+  return dim3(DynGeo<T, N>::THREADS);
+}
 template <int N, int W = 0>
 dim3 col_grid(const Dims& d, int groups) {
   constexpr int C = col_tile<N, W>();
@@ -109,7 +118,7 @@ hipError_t launch_steps_2s(RunView& r, int nsteps) {
       // next dynamics groups overwrite
       if (s + stage > 0) e = hipStreamWaitEvent(r.aux, rhs, 0);
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(rows_dyn_tasks<T>(r.ph)), dim3(64 * ROW_WAVES), 0, r.aux, P, r.d, r.ph,
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), (dyn_grid<T, N>()), (dyn_block<T, N>()), 0, r.aux, P, r.d, r.ph,
                          r.sched.remap);
       e = hipEventRecord(dyn, r.aux);
       launch_columns_part<T, N>(r, stage, 0, nd, r.aux);
@@ -140,7 +149,7 @@ void launch_steps_t(RunView& r, int nsteps) {
     for (int stage = 0; stage < 4; ++stage) {
       // time since the interval start, from integers
       const double sval = (double(r.n - r.n_tau) + c[stage]) * r.ph.dt;
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(rows_dyn_tasks<T>(r.ph)), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), (dyn_grid<T, N>()), (dyn_block<T, N>()), 0, r.stream, P, r.d,
                          r.ph, r.sched.remap);
       launch_rows_rhs<T, N>(r, P, sval);
       launch_columns_t<T, N>(r, stage);
@@ -175,7 +184,7 @@ hipError_t launch_steps_profiled_t(RunView& r, int nsteps, double* ms) {
       // start marker absorbs the work done at kernel boundaries, so each
       // interval covers one kernel's execution only
       (void)hipEventRecord(ev[e++], r.stream);
-      hipLaunchKernelGGL((k_rows_dyn<T, N>), row_grid<N>(rows_dyn_tasks<T>(r.ph)), dim3(64 * ROW_WAVES), 0, r.stream, P, r.d,
+      hipLaunchKernelGGL((k_rows_dyn<T, N>), (dyn_grid<T, N>()), (dyn_block<T, N>()), 0, r.stream, P, r.d,
                          r.ph, r.sched.remap);
       (void)hipEventRecord(ev[e++], r.stream);
       hipLaunchKernelGGL(k_drain<N>, dim3(1), dim3(64), 0, r.stream);
@@ -214,9 +223,9 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool
   const Dims d = Dims::make(N);
   const int rm = sc.remap;
   for (int stage = 0; stage < 4; ++stage) {
-    dim3 g1 = row_grid<N>(rows_dyn_ntask<T>());  // members with a prescribed flow end tasks 1, 2 at once
+    dim3 g1 = dyn_grid<T, N>();
     g1.z = nruns;
-    hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, dim3(64 * ROW_WAVES), 0, st, desc, rm);
+    hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, (dyn_block<T, N>()), 0, st, desc, rm);
     dim3 g2 = row_grid<N>(NRT);
     g2.z = nruns;
     const dim3 b2(64 * ROW_WAVES);

@@ -68,13 +68,6 @@ enum FieldSel : int { FS_ETA = 0, FS_ZETA, FS_U, FS_V, FS_Q /* (f + zeta) / h */
 // row-kernel tasks of the right-hand-side pass (the momentum rows, when
 // requested, are a kernel of their own with one task per component)
 enum RowTask : int { RT_XI = 0, RT_GB, RT_GT, RT_P, NRT = 4 };
-// tasks of the dynamics rows pass of float (three) and float64 runs (one; its
-// registers leave room for a single wave per SIMD); a prescribed flow needs
-// the first only
-template <typename T>
-__host__ __device__ constexpr int rows_dyn_ntask() {
-  return sizeof(T) == 4 ? 3 : 1;
-}
 
 // 2/3-rule cutoff: modes |kx|, |ky| <= K are kept (a compile-time constant of N)
 template <int N>
@@ -104,12 +97,6 @@ struct Phys {
   int kin;       // u, v, h prescribed: a linear plane wave plus a uniform flow (no dynamics)
   double kx, ky, A, omega, phase, U0, V0;  // kinematic: h' = A cos(kx x + ky y - omega t + phase)
 };
-
-// tasks of a single run's dynamics rows pass
-template <typename T>
-__host__ __device__ inline int rows_dyn_tasks(const Phys& ph) {
-  return ph.kin ? 1 : rows_dyn_ntask<T>();
-}
 
 // Column groups launched for a run, in slot order: first the groups that need
 // only the dynamics rows pass (u, v, h, and the Eulerian groups of fields other

@@ -280,16 +280,9 @@ __device__ __forceinline__ T field_value(int fs, const cplx<T>& uv, const cplx<T
   }
 }
 
-// One row of the dynamics rows pass, as ntask tasks.  Each task inverse-
-// transforms the row's (u, v) and (eta, zeta) and forms its products: task 0
-// stores the physical fields for the gathers, then zeta v, zeta u; task 1
-// K, eta u; task 2 eta v (one task: all of them).  Float runs take three short
-// waves per row instead of one long one, which keeps the SIMDs busy (one row
-// per wave leaves a single wave on each SIMD); the products are the same.  A
-// prescribed flow runs task 0 only.
 template <typename T, int N>
 __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& d, const Phys& ph, int rowblock,
-                                              int task, int ntask, cplx<T>* lds) {
+                                              cplx<T>* lds) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
   const int grp = row_group<NT>(), t = threadIdx.x % NT;
@@ -298,7 +291,6 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
   const size_t rf = d.rowfield_elems();
   const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
   constexpr int K = kcut<N>();
-  if (task > 0 && ph.kin) return;  // prescribed flow: only the physical fields
 
   cplx<T> uv[E], hz[E];
   load_pair<T, N, false, false>(uv, ICr + IC_U * rf, ICr + IC_V * rf, t);
@@ -325,57 +317,160 @@ __device__ __forceinline__ void rows_dyn_body(const StepPtrs<T>& P, const Dims& 
   }
   inverse_row<T, N>(hz, buf, t, P.tw);
 
+  // u, v and the two averaged fields, interleaved for the gathers
+  P4<T>* out = P.uvhz + (size_t)y * N;
   cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
   cplx<T> z[E];
-  if (task == 0) {
-    // u, v and the two averaged fields, interleaved for the gathers
-    P4<T>* out = P.uvhz + (size_t)y * N;
-    if (ph.fs0 == FS_ETA && ph.fs1 == FS_ZETA) {
+  if (ph.fs0 == FS_ETA && ph.fs1 == FS_ZETA) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, hz[e].x, hz[e].y};
-    } else {
+    for (int e = 0; e < E; ++e) out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, hz[e].x, hz[e].y};
+  } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        z[e] = {field_value<T>(ph.fs0, uv[e], hz[e], ph), field_value<T>(ph.fs1, uv[e], hz[e], ph)};
-        out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, z[e].x, z[e].y};
-      }
-      // their spectra, for the Eulerian means
-      if (ph.gen) forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_F0 * rf, RSr + RS_F1 * rf);
+    for (int e = 0; e < E; ++e) {
+      z[e] = {field_value<T>(ph.fs0, uv[e], hz[e], ph), field_value<T>(ph.fs1, uv[e], hz[e], ph)};
+      out[t + NT * e] = P4<T>{uv[e].x, uv[e].y, z[e].x, z[e].y};
     }
-    if (ph.kin) return;  // prescribed flow: no dynamics
-#pragma unroll
-    for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
-    forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
-    if (ntask > 1) return;
+    // their spectra, for the Eulerian means
+    if (ph.gen) forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_F0 * rf, RSr + RS_F1 * rf);
   }
-  if (task == 1 || ntask == 1) {
+  if (ph.kin) return;  // prescribed flow: no dynamics
+
+
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      z[e] = {T(0.5) * (uv[e].x * uv[e].x + uv[e].y * uv[e].y), hz[e].x * uv[e].x};  // K, eta u
-    forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
-    if (ntask > 1) return;
+  for (int e = 0; e < E; ++e) z[e] = {hz[e].y * uv[e].y, hz[e].y * uv[e].x};  // zeta v, zeta u
+  forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    z[e] = {T(0.5) * (uv[e].x * uv[e].x + uv[e].y * uv[e].y), hz[e].x * uv[e].x};  // K, eta u
+  forward_row<T, N, true, false>(z, buf, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
+#pragma unroll
+  for (int e = 0; e < E; ++e) z[e] = {hz[e].x * uv[e].y, T(0)};  // eta v
+  forward_row<T, N, false, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
+}
+
+// The dynamics rows pass of float runs: a block of three waves shares one
+// group of rows (WR = 64 / NT rows, one per lane group).  Wave 0 inverse-
+// transforms (u, v) and wave 1 (eta, zeta) into their LDS buffers; after a
+// barrier every wave forms its products from the shared physical values (wave
+// 0 also stores them for the gathers) -- wave 0 zeta v, zeta u; wave 1 K,
+// eta u; wave 2 eta v and, for other averaged fields, their values -- and
+// after a second barrier each forward-transforms its products in its own
+// buffer.  Five transforms per row, two deep, instead of five in a row on one
+// wave; the products and transforms are the same.
+template <typename T, int N>
+__device__ __forceinline__ void rows_dyn_coop(const StepPtrs<T>& P, const Dims& d, const Phys& ph, int rowblock,
+                                              cplx<T>* lds) {
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT, L = G::L, WR = 64 / NT;
+  constexpr int K = kcut<N>();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // the wave's role
+  const int lane = threadIdx.x % 64;
+  const int g = lane / NT, t = lane % NT;
+  const int y = rowblock * WR + g;
+  cplx<T>* b0 = lds + (0 * WR + g) * L;  // (u, v) after the first phase
+  cplx<T>* b1 = lds + (1 * WR + g) * L;  // (eta, zeta)
+  cplx<T>* bw = lds + (w * WR + g) * L;  // this wave's transform buffer afterwards
+  const size_t rf = d.rowfield_elems();
+  const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
+  cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
+  cplx<T> z[E];
+  if (w == 0) {
+    load_pair<T, N, false, false>(z, ICr + IC_U * rf, ICr + IC_V * rf, t);
+    inverse_row<T, N>(z, b0, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) b0[pidx(t + NT * e)] = z[e];
+  } else if (w == 1) {
+    // (eta + i zeta): zeta spectrum = i kx C_v - C_uy
+    const cplx<T>* Ch = ICr + IC_H * rf;
+    const cplx<T>* Cv = ICr + IC_V * rf;
+    const cplx<T>* Cuy = ICr + IC_UY * rf;
+    sched_fence();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int k = t + NT * r;
+      const bool lo = k <= K, hi = k >= N - K;
+      const int kk = min(lo ? k : N - k, K);
+      cplx<T> a = Ch[kk];
+      const cplx<T> cv = Cv[kk], cu = Cuy[kk];
+      cplx<T> b = {-T(kk) * cv.y - cu.x, T(kk) * cv.x - cu.y};
+      const T sy = (kk == 0) ? T(0) : (hi ? T(-1) : T(1));
+      a.y *= sy;
+      b.y *= sy;
+      z[r] = (lo || hi) ? cplx<T>{a.x - b.y, a.y + b.x} : cplx<T>{T(0), T(0)};
+    }
+    inverse_row<T, N>(z, b1, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) b1[pidx(t + NT * e)] = z[e];
   }
-  {
+  __syncthreads();
+  const bool dyn = !ph.kin;  // a prescribed flow needs the physical fields only
+  cplx<T> zf[E];             // wave 2: the averaged fields (other than eta, zeta)
+  if (w == 0) {
+    // u, v and the two averaged fields, interleaved for the gathers; zeta v, zeta u
+    P4<T>* out = P.uvhz + (size_t)y * N;
+    const bool plain = (ph.fs0 == FS_ETA && ph.fs1 == FS_ZETA);
 #pragma unroll
-    for (int e = 0; e < E; ++e) z[e] = {hz[e].x * uv[e].y, T(0)};  // eta v
-    forward_row<T, N, false, false>(z, buf, t, P.tw, RSr + RS_HV * rf, nullptr);
+    for (int e = 0; e < E; ++e) {
+      const cplx<T> uv = b0[pidx(t + NT * e)], hz = b1[pidx(t + NT * e)];
+      if (plain) out[t + NT * e] = P4<T>{uv.x, uv.y, hz.x, hz.y};
+      else out[t + NT * e] = P4<T>{uv.x, uv.y, field_value<T>(ph.fs0, uv, hz, ph), field_value<T>(ph.fs1, uv, hz, ph)};
+      z[e] = {hz.y * uv.y, hz.y * uv.x};
+    }
+  } else if (w == 1) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cplx<T> uv = b0[pidx(t + NT * e)], hz = b1[pidx(t + NT * e)];
+      z[e] = {T(0.5) * (uv.x * uv.x + uv.y * uv.y), hz.x * uv.x};  // K, eta u
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cplx<T> uv = b0[pidx(t + NT * e)], hz = b1[pidx(t + NT * e)];
+      z[e] = {hz.x * uv.y, T(0)};  // eta v
+      if (ph.gen) zf[e] = {field_value<T>(ph.fs0, uv, hz, ph), field_value<T>(ph.fs1, uv, hz, ph)};
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    if (dyn) forward_row<T, N, true, false>(z, bw, t, P.tw, RSr + RS_ZV * rf, RSr + RS_ZU * rf);
+  } else if (w == 1) {
+    if (dyn) forward_row<T, N, true, false>(z, bw, t, P.tw, RSr + RS_K * rf, RSr + RS_HU * rf);
+  } else {
+    // the averaged fields' spectra, for the Eulerian means
+    if (ph.gen) forward_row<T, N, true, false>(zf, bw, t, P.tw, RSr + RS_F0 * rf, RSr + RS_F1 * rf);
+    if (dyn) forward_row<T, N, false, false>(z, bw, t, P.tw, RSr + RS_HV * rf, nullptr);
   }
 }
 
-// float: three resident waves per SIMD (at most 168 registers), one per task
-// of a row
+// Geometry of the dynamics rows pass: float runs take blocks of three waves
+// sharing one group of rows; float64 (whose registers leave room for one wave
+// per SIMD) blocks of ROW_WAVES waves, one row group each, every product on
+// the row's own wave.
+template <typename T, int N>
+struct DynGeo {
+  static constexpr bool COOP = sizeof(T) == 4;
+  static constexpr int WR = 64 / RowGeo<N>::NT;  // rows per wave
+  static constexpr int THREADS = COOP ? 3 * 64 : 64 * ROW_WAVES;
+  static constexpr int RPB = COOP ? WR : RowGeo<N>::RPB;  // rows per block
+  static constexpr int LDS = (COOP ? 3 * WR : RowGeo<N>::RPB) * RowGeo<N>::L;
+  static_assert(RowGeo<N>::NT <= 64 && 64 % RowGeo<N>::NT == 0, "row groups within a wave");
+};
+
+// float: three resident waves per SIMD (at most 168 registers): one block of
+// the cooperative form on each
 template <typename T>
 __host__ __device__ constexpr int dyn_waves() {
   return sizeof(T) == 4 ? 3 : 1;
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES, (dyn_waves<T>())) k_rows_dyn(StepPtrs<T> P, Dims d, Phys ph,
-                                                                              int remap) {
-  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
-  int rowblock, task, z;
-  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);  // grid = (row blocks, tasks)
-  rows_dyn_body<T, N>(P, d, ph, rowblock, task, (int)gridDim.y, lds);
+__global__ void __launch_bounds__((DynGeo<T, N>::THREADS), (dyn_waves<T>())) k_rows_dyn(StepPtrs<T> P, Dims d,
+                                                                                       Phys ph, int remap) {
+  __shared__ cplx<T> lds[DynGeo<T, N>::LDS];
+  int rowblock, unused, z;
+  xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
+  if constexpr (DynGeo<T, N>::COOP) rows_dyn_coop<T, N>(P, d, ph, rowblock, lds);
+  else rows_dyn_body<T, N>(P, d, ph, rowblock, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -1105,12 +1200,13 @@ __global__ void __launch_bounds__((col_threads<N, W>()), (col_waves<T, N, false>
 // --------------------------------------------------------------------------
 
 template <typename T, int N>
-__global__ void __launch_bounds__(64 * ROW_WAVES, (dyn_waves<T>())) k_rows_dyn_b(const RunDesc<T>* __restrict__ runs,
-                                                                                int remap) {
-  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
-  int rowblock, task, z;
-  xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);
-  rows_dyn_body<T, N>(runs[z].P, Dims::make(N), runs[z].ph, rowblock, task, (int)gridDim.y, lds);
+__global__ void __launch_bounds__((DynGeo<T, N>::THREADS), (dyn_waves<T>())) k_rows_dyn_b(
+    const RunDesc<T>* __restrict__ runs, int remap) {
+  __shared__ cplx<T> lds[DynGeo<T, N>::LDS];
+  int rowblock, unused, z;
+  xcd_split(gridDim.x, 1, rowblock, unused, z, remap);
+  if constexpr (DynGeo<T, N>::COOP) rows_dyn_coop<T, N>(runs[z].P, Dims::make(N), runs[z].ph, rowblock, lds);
+  else rows_dyn_body<T, N>(runs[z].P, Dims::make(N), runs[z].ph, rowblock, lds);
 }
 
 template <typename T, int N, bool CUB>
