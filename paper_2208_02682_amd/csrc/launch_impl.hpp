@@ -79,7 +79,7 @@ void launch_columns_t(RunView& r, int stage) {
 // the rows pass of the mean right-hand sides, and the momentum rows when requested
 template <typename T, int N>
 void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
-  const dim3 g = row_grid<N>(NRT), b(64 * ROW_WAVES);
+  const dim3 g = row_grid<N>(rhs_tasks<T, N>()), b(64 * ROW_WAVES);
   const int rm = r.sched.remap;
   if (r.cubic) hipLaunchKernelGGL((k_rows_rhs<T, N, true>), g, b, 0, r.stream, P, r.d, sval, rm);
   else hipLaunchKernelGGL((k_rows_rhs<T, N, false>), g, b, 0, r.stream, P, r.d, sval, rm);
@@ -226,7 +226,7 @@ void launch_batch_step_t(hipStream_t st, const RunDesc<T>* desc, int nruns, bool
     dim3 g1 = dyn_grid<T, N>();
     g1.z = nruns;
     hipLaunchKernelGGL((k_rows_dyn_b<T, N>), g1, (dyn_block<T, N>()), 0, st, desc, rm);
-    dim3 g2 = row_grid<N>(NRT);
+    dim3 g2 = row_grid<N>(rhs_tasks<T, N>());
     g2.z = nruns;
     const dim3 b2(64 * ROW_WAVES);
     if (cubic) hipLaunchKernelGGL((k_rows_rhs_b<T, N, true>), g2, b2, 0, st, desc, stage, rm);

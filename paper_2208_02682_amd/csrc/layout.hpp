@@ -65,9 +65,21 @@ enum ColGroup : int {
 // the fields the two averaging slots can hold (f_0, f_1; the default is (eta, zeta))
 enum FieldSel : int { FS_ETA = 0, FS_ZETA, FS_U, FS_V, FS_Q /* (f + zeta) / h */ };
 
-// row-kernel tasks of the right-hand-side pass (the momentum rows, when
-// requested, are a kernel of their own with one task per component)
-enum RowTask : int { RT_XI = 0, RT_GB, RT_GT, RT_P, NRT = 4 };
+// row-kernel tasks of the right-hand-side pass.  Two-task form (float, N >=
+// 512): strategy 2 (xi and g-bar), and strategy 1 with the Lagrangian-mean
+// velocity (g-tilde and P).  Four-task form: xi, g-bar, g-tilde, P.  The
+// momentum rows, when requested, are a kernel of their own with one task per
+// component.
+enum RowTask : int { RT_S2 = 0, RT_S1 };
+enum RowTask4 : int { RT4_XI = 0, RT4_GB, RT4_GT, RT4_P };
+template <typename T, int N>
+__host__ __device__ constexpr bool rhs_merged() {
+  return sizeof(T) == 4 && N >= 512;
+}
+template <typename T, int N>
+__host__ __device__ constexpr int rhs_tasks() {
+  return rhs_merged<T, N>() ? 2 : 4;
+}
 
 // 2/3-rule cutoff: modes |kx|, |ky| <= K are kept (a compile-time constant of N)
 template <int N>

@@ -476,13 +476,15 @@ __global__ void __launch_bounds__((DynGeo<T, N>::THREADS), (dyn_waves<T>())) k_r
 // --------------------------------------------------------------------------
 // rows_rhs
 // --------------------------------------------------------------------------
-// tasks (one wavefront per row and task; four light tasks keep the register
-// footprint, hence occupancy, reasonable):
-//   RT_XI  strategy 2, both xi components (eq. (4.5a))
-//   RT_GB  strategy 2, g-bar of eta and zeta (eq. (4.5b))
-//   RT_GT  strategy 1, g-tilde of eta and zeta (eq. (4.1))
-//   RT_P   strategy 1, both P components (eq. (3.9) in P form)
-// The two strategy-2 tasks each transform xi and gather at x + xi.
+// Tasks, one wavefront per row and task.  Float runs of N >= 512 take two:
+//   RT_S2  strategy 2: both xi components (eq. (4.5a)) and g-bar of eta and
+//          zeta (eq. (4.5b)), from one transform of xi and one gather
+//   RT_S1  strategy 1: g-tilde of eta and zeta (eq. (4.1)) and both P
+//          components (eq. (3.9) in P form)
+// (each wave holds two output pairs; the rows' 2N waves at two per SIMD run in
+// one round).  Smaller grids and float64, where more, shorter waves pay
+// better, take four: RT4_XI (xi), RT4_GB (g-bar), RT4_GT (g-tilde), RT4_P (P),
+// the two strategy-2 tasks each transforming xi and gathering at x + xi.
 // gathers of (u, v) (PAIR 0) or (eta, zeta) (PAIR 1) at x + xi for the E points
 // of a lane, in place of the displacements held in a
 template <typename T, int N, bool CUB, int PAIR>
@@ -505,8 +507,122 @@ __device__ __forceinline__ void gather_row(cplx<T> (&a)[fft_E<N>()], const P4<T>
   }
 }
 
+// The mean right-hand-side rows pass, two tasks per row.
+// Task 0, strategy 2: with w = xi / (t - tau) the partial-mean velocity (u / 2
+// at t = tau, SPOS false), the gathered terms at x + xi less w . grad of
+// (xi_x, xi_y) and of (g-bar_h, g-bar_zeta): one transform of xi serves both,
+// and one gather of the interleaved point serves all four fields.
+template <typename T, int N, bool CUB, bool SPOS>
+__device__ __forceinline__ void rows_rhs_s2(const StepPtrs<T>& P, const Dims& d, double s, int y, int t,
+                                            cplx<T>* buf, cplx<T>* xs) {
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT;
+  const size_t rf = d.rowfield_elems();
+  const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
+  cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
+  const P4<T>* F = P.uvhz;
+  const P4<T>* Fr = P.uvhz + (size_t)y * N;
+  const T inv_s = SPOS ? T(1.0 / s) : T(0);
+  // w at point e from xi
+  auto wof = [&](int e, cplx<T> xi) -> cplx<T> {
+    if constexpr (SPOS) {
+      return {xi.x * inv_s, xi.y * inv_s};
+    } else {
+      const P4<T> q = Fr[t + NT * e];
+      return {T(0.5) * q.u, T(0.5) * q.v};
+    }
+  };
+  cplx<T> a[E], guv[E], ghz[E], b[E];
+  // displacement xi, kept in the row's second LDS buffer (xs) after the gathers
+  load_pair<T, N, false, false>(a, ICr + IC_XIX * rf, ICr + IC_XIY * rf, t);
+  inverse_row<T, N>(a, buf, t, P.tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) xs[pidx(t + NT * e)] = a[e];
+  // gathered (u, v) less w, and (eta, zeta), at x + xi
+  if constexpr (CUB) {
+    // cubic gathers: 16 corners per point, one point in flight at a time
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cplx<T> w = wof(e, a[e]);
+      const cplx<T> g = gather2_cubic<T, N, 0>(F, t + NT * e, y, a[e].x, a[e].y);
+      guv[e] = {g.x - w.x, g.y - w.y};
+      ghz[e] = gather2_cubic<T, N, 1>(F, t + NT * e, y, a[e].x, a[e].y);
+      sched_fence();
+    }
+  } else {
+    constexpr int GG = 4;  // points with their loads in flight together
+    static_assert(E % GG == 0, "gather groups");
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += GG) {
+#pragma unroll
+      for (int e = e0; e < e0 + GG; ++e) {
+        const cplx<T> w = wof(e, a[e]);
+        const P4<T> g = gather4<T, N>(F, t + NT * e, y, a[e].x, a[e].y);
+        guv[e] = {g.u - w.x, g.v - w.y};
+        ghz[e] = {g.h, g.z};
+      }
+      sched_fence();
+    }
+  }
+  // less w . grad of each component (a rolled loop: unrolled, the compiler
+  // interleaves the four transforms and runs out of registers)
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int f = (c == 0) ? IC_XIX : (c == 1) ? IC_XIY : (c == 2) ? IC_GBH : IC_GBZ;
+    load_pair<T, N, true, false>(b, ICr + f * rf, ICr + (f + 1) * rf, t);
+    inverse_row<T, N>(b, buf, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cplx<T> w = wof(e, xs[pidx(t + NT * e)]);
+      const T dw = w.x * b[e].x + w.y * b[e].y;
+      if (c == 0) guv[e].x = guv[e].x - dw;
+      else if (c == 1) guv[e].y = guv[e].y - dw;
+      else if (c == 2) ghz[e].x = ghz[e].x - dw;
+      else ghz[e].y = ghz[e].y - dw;
+    }
+    sched_fence();
+  }
+  forward_row<T, N, true>(guv, buf, t, P.tw, RSr + RS_XIX * rf, RSr + RS_XIY * rf);
+  forward_row<T, N, true>(ghz, buf, t, P.tw, RSr + RS_GBH * rf, RSr + RS_GBZ * rf);
+}
+
+// Task 1, strategy 1 and the Lagrangian-mean velocity: f - u . grad g-tilde
+// (f = eta, zeta) and (t - tau) u - u . grad P; the velocity is re-read where
+// it is used.
+template <typename T, int N>
+__device__ __forceinline__ void rows_rhs_s1(const StepPtrs<T>& P, const Dims& d, double s, int y, int t,
+                                            cplx<T>* buf) {
+  using G = RowGeo<N>;
+  constexpr int E = G::E, NT = G::NT;
+  const size_t rf = d.rowfield_elems();
+  const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
+  cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
+  const P4<T>* Fr = P.uvhz + (size_t)y * N;
+  const T sT = T(s);
+  cplx<T> agt[E], apx[E], b[E];
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int f = (c == 0) ? IC_GTH : (c == 1) ? IC_GTZ : (c == 2) ? IC_PX : IC_PY;
+    load_pair<T, N, true, false>(b, ICr + f * rf, ICr + (f + 1) * rf, t);
+    inverse_row<T, N>(b, buf, t, P.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const P4<T> q = Fr[t + NT * e];
+      const T src = (c == 0) ? q.h : (c == 1) ? q.z : (c == 2) ? sT * q.u : sT * q.v;
+      const T r = src - (q.u * b[e].x + q.v * b[e].y);
+      if (c == 0) agt[e].x = r;
+      else if (c == 1) agt[e].y = r;
+      else if (c == 2) apx[e].x = r;
+      else apx[e].y = r;
+    }
+    sched_fence();
+  }
+  forward_row<T, N, true>(agt, buf, t, P.tw, RSr + RS_GTH * rf, RSr + RS_GTZ * rf);
+  forward_row<T, N, true>(apx, buf, t, P.tw, RSr + RS_PX * rf, RSr + RS_PY * rf);
+}
+
 template <typename T, int N, bool CUB>
-__device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
+__device__ __forceinline__ void rows_rhs_body4(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
                                               int task, cplx<T>* lds) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
@@ -521,7 +637,7 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
   constexpr int K = kcut<N>();
 
   cplx<T> a[E], b[E];
-  if (task == RT_XI || task == RT_GB) {
+  if (task == RT4_XI || task == RT4_GB) {
     // displacement xi, partial-mean velocity w = xi / (t - tau) (u/2 at t = tau)
     load_pair<T, N, false, false>(a, ICr + IC_XIX * rf, ICr + IC_XIY * rf, t);
     inverse_row<T, N>(a, buf, t, P.tw);
@@ -541,7 +657,7 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
     // gathered terms at x + xi, in groups of GG points (bounds loads in flight)
     constexpr int GG = 4;
     static_assert(E % GG == 0, "gather groups");
-    const bool xi_task = (task == RT_XI);
+    const bool xi_task = (task == RT4_XI);
     if constexpr (CUB) {
       // cubic gathers: 16 corners per point, one point in flight at a time
 #pragma unroll
@@ -586,7 +702,7 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
     forward_row<T, N, true>(a, buf, t, P.tw, RSr + o * rf, RSr + (o + 1) * rf);
   } else {
     // f - u . grad g-tilde (f = eta, zeta), or (t - tau) u - u . grad P
-    const bool gt = (task == RT_GT);
+    const bool gt = (task == RT4_GT);
     const T sT = T(s);
     cplx<T> uv[E];
 #pragma unroll
@@ -614,10 +730,43 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
   }
 }
 
+template <typename T, int N, bool CUB>
+__device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
+                                              int task, cplx<T>* lds) {
+  using G = RowGeo<N>;
+  constexpr int NT = G::NT;
+  if constexpr (!rhs_merged<T, N>()) {
+    rows_rhs_body4<T, N, CUB>(P, d, s, rowblock, task, lds);
+    return;
+  }
+  const int grp = row_group<NT>(), t = threadIdx.x % NT;
+  const int y = rowblock * G::RPB + grp;  // the grid covers the rows exactly
+  cplx<T>* buf = lds + grp * G::L;
+  if (task == RT_S2) {
+    cplx<T>* xs = lds + (G::RPB + grp) * G::L;
+    if (s > 0.0) rows_rhs_s2<T, N, CUB, true>(P, d, s, y, t, buf, xs);
+    else rows_rhs_s2<T, N, CUB, false>(P, d, s, y, t, buf, xs);
+  } else {
+    rows_rhs_s1<T, N>(P, d, s, y, t, buf);
+  }
+}
+
+// two-task form: two resident waves per SIMD, as many as its two LDS buffers
+// per row allow, so that every row's two tasks are resident at once
+template <typename T, int N>
+__host__ __device__ constexpr int rhs_waves() {
+  return rhs_merged<T, N>() ? 2 : 1;
+}
+template <typename T, int N>
+__host__ __device__ constexpr int rhs_lds() {
+  return (rhs_merged<T, N>() ? 2 : 1) * RowGeo<N>::RPB * RowGeo<N>::L;
+}
+
 // CUB: cubic instead of bilinear strategy-2 gathers
 template <typename T, int N, bool CUB>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs(StepPtrs<T> P, Dims d, double s, int remap) {
-  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+__global__ void __launch_bounds__(64 * ROW_WAVES, (rhs_waves<T, N>())) k_rows_rhs(StepPtrs<T> P, Dims d, double s,
+                                                                              int remap) {
+  __shared__ cplx<T> lds[rhs_lds<T, N>()];  // transform buffers (and xi, two-task form)
   int rowblock, task, z;
   xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);  // grid = (row blocks, tasks)
   rows_rhs_body<T, N, CUB>(P, d, s, rowblock, task, lds);
@@ -1210,8 +1359,9 @@ __global__ void __launch_bounds__((DynGeo<T, N>::THREADS), (dyn_waves<T>())) k_r
 }
 
 template <typename T, int N, bool CUB>
-__global__ void __launch_bounds__(64 * ROW_WAVES) k_rows_rhs_b(const RunDesc<T>* __restrict__ runs, int stage, int remap) {
-  __shared__ cplx<T> lds[RowGeo<N>::RPB * RowGeo<N>::L];
+__global__ void __launch_bounds__(64 * ROW_WAVES, (rhs_waves<T, N>())) k_rows_rhs_b(const RunDesc<T>* __restrict__ runs,
+                                                                                int stage, int remap) {
+  __shared__ cplx<T> lds[rhs_lds<T, N>()];  // transform buffers (and xi, two-task form)
   int rowblock, task, z;
   xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);
   const RunDesc<T>& R = runs[z];
