@@ -566,7 +566,7 @@ __device__ __forceinline__ void rows_rhs_s2(const StepPtrs<T>& P, const Dims& d,
   }
   // less w . grad of each component (a rolled loop: unrolled, the compiler
   // interleaves the four transforms and runs out of registers)
-#pragma unroll 1
+#pragma unroll 2
   for (int c = 0; c < 4; ++c) {
     const int f = (c == 0) ? IC_XIX : (c == 1) ? IC_XIY : (c == 2) ? IC_GBH : IC_GBZ;
     load_pair<T, N, true, false>(b, ICr + f * rf, ICr + (f + 1) * rf, t);
@@ -600,7 +600,7 @@ __device__ __forceinline__ void rows_rhs_s1(const StepPtrs<T>& P, const Dims& d,
   const P4<T>* Fr = P.uvhz + (size_t)y * N;
   const T sT = T(s);
   cplx<T> agt[E], apx[E], b[E];
-#pragma unroll 1
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int f = (c == 0) ? IC_GTH : (c == 1) ? IC_GTZ : (c == 2) ? IC_PX : IC_PY;
     load_pair<T, N, true, false>(b, ICr + f * rf, ICr + (f + 1) * rf, t);
