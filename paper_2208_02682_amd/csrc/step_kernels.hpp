@@ -982,12 +982,19 @@ __device__ __forceinline__ void tile_load(const ColCtx<T, N, C>& cx, const cplx<
   __syncthreads();
 }
 
+// block-wide: the C buffers to rows of a [N][NKXP] field (columns kx0..).  The
+// block is C * N / E threads, a compile-time count, so the loop unrolls and all
+// of a thread's LDS reads are issued before its stores.
 template <typename T, int N, int C>
 __device__ __forceinline__ void tile_store(const ColCtx<T, N, C>& cx, cplx<T>* __restrict__ dst,
                                            const Dims& d) {
   constexpr int LC = ColCtx<T, N, C>::LC;
+  constexpr int NTH = C * (N / fft_E<N>());
+  static_assert((N * C) % NTH == 0, "tile store rounds");
   __syncthreads();
-  for (int i = threadIdx.x; i < N * C; i += blockDim.x) {
+#pragma unroll
+  for (int i0 = 0; i0 < N * C; i0 += NTH) {
+    const int i = i0 + (int)threadIdx.x;
     const int c = i % C, y = i / C;
     const int kx = cx.kx0 + c;
     if (kx <= kcut<N>()) dst[(size_t)y * d.NKXP + kx] = cx.lds[c * LC + pidx(y)];
