@@ -1026,6 +1026,32 @@ __device__ __forceinline__ cplx<T> column_value(const ColCtx<T, N, C>& cx, int r
   return {q.x * inv, q.y * inv};
 }
 
+// forward column transform of A - i kx B for two row-spectrum fields: a
+// column's kx is fixed, so the x-derivative of B joins A before one transform
+// (the transform is linear).  Returns the masked, 1/N^2-normalised values at
+// k = t + NT r.
+template <typename T, int N, int C>
+__device__ __forceinline__ void column_forward_dx(const ColCtx<T, N, C>& cx, const cplx<T>* srcA,
+                                                  const cplx<T>* srcB, const Dims& d,
+                                                  const cplx<T>* __restrict__ tw, cplx<T> (&out)[fft_E<N>()]) {
+  constexpr int E = fft_E<N>(), NT = N / E;
+  tile_load<T, N, C>(cx, srcA, d);
+  cplx<T> v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = cx.buf[pidx(cx.t + NT * r)];
+  tile_load<T, N, C>(cx, srcB, d);  // its opening barrier: every wave has read A
+  const T kxT = T(cx.kx);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const cplx<T> b = cx.buf[pidx(cx.t + NT * r)];
+    v[r] = {v[r].x + kxT * b.y, v[r].y - kxT * b.x};
+  }
+  xsync<NT>();
+  fft<T, N, fft_E<N>(), -1>(v, cx.buf, cx.t, tw);
+#pragma unroll
+  for (int r = 0; r < E; ++r) out[r] = column_value<T, N, C>(cx, r);
+}
+
 // forward column transform of one row-spectrum field; returns the masked,
 // 1/N^2-normalised right-hand-side values at k = t + NT r
 template <typename T, int N, int C>
@@ -1126,8 +1152,13 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
   cplx<T> r0[E];
   // a kinematic run has no dynamics right-hand sides
   if (stage >= 0 && !(DYN && ph.kin)) {
-    column_forward<T, N, C>(cx, P.RS + F0 * rf, d, P.tw, r0);
-    if constexpr (NF == 2) column_forward_lds<T, N, C>(cx, P.RS + F1 * rf, d, P.tw);
+    if constexpr (G == CG_U) {
+      // zeta v - i kx K in one transform
+      column_forward_dx<T, N, C>(cx, P.RS + F0 * rf, P.RS + F1 * rf, d, P.tw, r0);
+    } else {
+      column_forward<T, N, C>(cx, P.RS + F0 * rf, d, P.tw, r0);
+      if constexpr (NF == 2) column_forward_lds<T, N, C>(cx, P.RS + F1 * rf, d, P.tw);
+    }
   }
 
   // state of this group
@@ -1182,10 +1213,13 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     // could alias later loads as far as the compiler knows, which would
     // otherwise serialise the coefficients).
     // The Eulerian accumulators of the default averaged fields ride along with
-    // the g-tilde groups (E_eta with g-tilde_h, E_zeta with g-tilde_zeta): they
-    // read the stage values but need no transform, and the dynamics groups
-    // already move the most data.  (Other averaged fields: groups CG_EF0/EF1.)
-    constexpr bool EULA = (G == CG_GTH), EULB = (G == CG_GTZ);
+    // the g-tilde and g-bar groups (E_eta with the h groups, E_zeta with the
+    // zeta groups; the g-tilde group takes the even batch positions r, the
+    // g-bar group the odd ones): they read the stage values but need no
+    // transform, and the dynamics groups already move the most data.  (Other
+    // averaged fields: groups CG_EF0/EF1.)
+    constexpr bool EULA = (G == CG_GTH || G == CG_GBH), EULB = (G == CG_GTZ || G == CG_GBZ);
+    constexpr int EPAR = (G == CG_GTH || G == CG_GTZ) ? 0 : 1;
     const bool eul = (EULA || EULB) && !ph.gen;
     constexpr int RB0 = (DBL || DYN || EULA || EULB) ? 4 : 8;
     constexpr int RB = (E % RB0 == 0) ? RB0 : 4;
@@ -1216,7 +1250,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         }
         rk4_load<TS>(stage, Y + j, YL + j, A + j, y[q], lo[q], a[q]);
         if constexpr (EULA || EULB) {
-          if (eul) {
+          if (eul && (r0i + q) % 2 == EPAR) {
             constexpr int se = EULA ? SF_EH : SF_EZ;
             if constexpr (EULA) {
               sh[q] = Ys_in[2 * sp + j];
@@ -1239,7 +1273,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         if constexpr (EULA || EULB) {
           // Eulerian accumulators from the stage values: dE_eta/dt = eta (h less H
           // at k = 0), dE_zeta/dt = i kx v - i ky u
-          if (eul) {
+          if (eul && r % 2 == EPAR) {
             constexpr int se = EULA ? SF_EH : SF_EZ;
             cplx<T> f;
             if constexpr (EULA) {
@@ -1256,10 +1290,9 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         const T hv = T(ph.nu8 * (k2 * k2) * (k2 * k2));
         cplx<T> R;
         if constexpr (G == CG_U) {
-          // zeta v + f v - i kx (g h + K) - nu8 |k|^8 u
+          // (zeta v - i kx K) + f v - i kx g h - nu8 |k|^8 u
           const cplx<T> u = su[q], v = sv[q], h = sh[q];
-          const cplx<T> r1 = column_value<T, N, C>(cx, r);
-          const cplx<T> B = {gT * h.x + r1.x, gT * h.y + r1.y};
+          const cplx<T> B = {gT * h.x, gT * h.y};
           R = {r0[r].x + fT * v.x + kxT * B.y - hv * u.x, r0[r].y + fT * v.y - kxT * B.x - hv * u.y};
         } else if constexpr (G == CG_V) {
           // -zeta u - f u - i ky (g h + K) - nu8 |k|^8 v
