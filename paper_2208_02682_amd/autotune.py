@@ -53,7 +53,7 @@ def load_default(arch: Optional[str] = None) -> int:
 
 
 def tune(specs: Iterable[Tuple[int, str]], config_for: Callable[[int, str], Config],
-         state_for: Callable[[int], tuple], *, warm_steps: int = 20, steps: int = 8, reps: int = 3) -> List[dict]:
+         state_for: Callable[[int], tuple], *, warm_steps: int = 20, steps: int = 64, reps: int = 5) -> List[dict]:
     """Autotune every (N, precision) of specs on a run made with config_for(N,
     precision) from the state state_for(N), after warm_steps steps of an open
     interval (so that the strategy-2 gathers reach as far as in a running
