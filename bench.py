@@ -99,9 +99,17 @@ def algorithmic_bytes(N: int, fp32: bool):
     # accumulator read (stages 2-4) and written (stages 1-3), Y written (stage 4),
     # stage values of u, v, h read and written; float32 state also reads and
     # writes its trailing words in stage 4 (compensated RK4 update)
-    comp = (0.25 + 0.25) * 9 * sp * cT if fp32 else 0.0
+    comp = compensation_bytes(N) if fp32 else 0.0
     columns = 13 * rowfield + 20 * rowfield + (1.0 + 0.75 + 0.75 + 0.25) * state + 6 * sp * cT + comp
     return {"rows_dyn": rows_dyn, "rows_rhs": rows_rhs, "columns": columns}
+
+
+def compensation_bytes(N: int) -> float:
+    """Bytes per column launch (averaged over the 4 stages) of the trailing words
+    of the compensated float32 state: 9 fields, read and written in stage 4."""
+    K = (N - 1) // 3
+    sp = (K + 1) * (2 * K + 1)
+    return (0.25 + 0.25) * 9 * sp * 8
 
 
 def cpu_baseline(w, seconds: float):
@@ -724,6 +732,14 @@ def main(argv=None) -> int:
                      "note": "lm_remap_s1 on the interval closed after the profiled pass (host wall clock, "
                              "synchronous call); once per interval, not in the step"},
     }
+    if fp32:
+        # the compensated float32 state: its trailing words are read and written
+        # in stage 4 of the column pass (algorithmic bytes, per launch averaged
+        # over the 4 stages, and per step)
+        comp = compensation_bytes(w.N)
+        rec["compensation"] = {"bytes_per_column_launch": comp, "bytes_per_step": 4 * comp,
+                               "share_of_step_bytes": 4 * comp / step_bytes,
+                               "ms_per_step_at_hbm_rate": 4 * comp / (step_bytes * a.steps / (ms * 1e-3)) * 1e3}
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     run.close()
