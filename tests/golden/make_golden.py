@@ -8,7 +8,7 @@ full-grid L2 norm of each output (heights as h - H).
 
     python tests/golden/make_golden.py sw256_fp64 --stride 8
     python tests/golden/make_golden.py sw1024recipe_at256_fp32 --stride 8
-    python tests/golden/make_golden.py sw1024_fp32 --stride 16 --threads 6 --intervals 1 --checkpoint /tmp/g1024.npz
+    python tests/golden/make_golden.py sw1024_fp32 --stride 4 --threads 6 --checkpoint /tmp/g1024.npz
 
 The output is tests/golden/<workload>.npz.  With --checkpoint, the oracle's
 state is saved every --checkpoint-every steps and a rerun resumes from it.
