@@ -81,22 +81,24 @@ def test_1024_recipe_at_256_mixed_two_intervals():
 # state, float64 xi and P), both intervals at every 4th point: the strategy-1
 # means of h (interval 0: 1.018e-5, interval 1: 1.025e-5) and of zeta (interval
 # 1: 1.025e-5) are just above the bar; every other output is below it (largest
-# 6.6e-6).  The strategy-1 accumulators g-tilde = (t - tau) f-tilde grow over
-# the interval, and their advection term u . grad g-tilde is evaluated in
-# float32 at every stage; the compensated state removed the rounding of the
-# state itself (the 256^2 recipe's strategy-1 error fell from 6.0e-5 to
-# 5.3e-6), and one float32 rounding of the initial state moves the outputs by
-# at most 3.8e-7.  The bar is not widened: these three outputs have a test of
-# their own, marked as an expected failure.
+# 6.6e-6).  Against the float64 GPU path (itself within 7.6e-14 of the oracle
+# here): the instantaneous state is off by at most 6e-7 (eta) after a quarter
+# interval and 4e-6 after a whole one, but the Lagrangian means of eta are about
+# eight times smaller than eta (its waves average out), while the strategy-1
+# right-hand side, eta - u . grad g-tilde with g-tilde = (t - tau) f-tilde, is
+# of the size of eta and its advection part grows with t - tau.  The float32
+# rounding of that right-hand side, relative to its own size, is amplified in
+# the mean, and the error grows with the interval length (S1 mean h 4.3e-6,
+# 6.2e-6, 1.02e-5 over a quarter, half and whole interval); it lies in
+# wavenumbers 16-400, not in the spatial mean.  The bar is not widened: these
+# three outputs have a test of their own, marked as an expected failure.
 KNOWN_ABOVE = {(0, "S1_mean:h"), (1, "S1_mean:h"), (1, "S1_mean:zeta")}
 
 
-@pytest.fixture(scope="module")
-def errors_1024():
-    """The 1024^2 mixed-precision workload at its full size, in the launch
-    schedule bench.py uses (the shipped schedule cache), over every stored
-    interval (2 x 4676 RK4 steps), against the float64 oracle's values at every
-    4th point."""
+def _errors_1024(precision=None):
+    """The 1024^2 workload at its full size, in the shipped launch schedules
+    (the ones bench.py uses), over every stored interval (2 x 4676 RK4 steps),
+    against the float64 oracle's values at every 4th point."""
     import paper_2208_02682_amd as L
     from paper_2208_02682_amd import autotune as at
     name = "sw1024_fp32"
@@ -105,13 +107,25 @@ def errors_1024():
     at.load_default()
     try:
         say(f"  schedules: fp32 {L.get_schedule(1024, 'fp32')}, fp64 {L.get_schedule(1024, 'fp64')}")
-        _, errs = _errors(name)
+        _, errs = _errors(name, precision)
     finally:
         for n in (64, 128, 192, 256, 384, 512, 1024):
             for p in ("fp32", "fp64"):
                 L.set_schedule(n, p, 0, 1)
                 L.set_schedule(n, p, 0, 1, batched=True)
     return errs
+
+
+@pytest.fixture(scope="module")
+def errors_1024():
+    """The mixed-precision path (the workload's own precision)."""
+    return _errors_1024()
+
+
+def test_sw1024_fp64_at_full_size():
+    """The same 1024^2 run entirely in float64: every output of both intervals
+    within 1e-12 of the oracle (measured at most 7.6e-14)."""
+    _check(_errors_1024("fp64"), TOL64)
 
 
 def test_sw1024_mixed_at_full_size(errors_1024):
