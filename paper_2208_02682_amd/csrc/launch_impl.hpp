@@ -81,8 +81,9 @@ template <typename T, int N>
 void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
   const dim3 g = row_grid<N>(rhs_tasks<T, N>()), b(64 * ROW_WAVES);
   const int rm = r.sched.remap;
-  if (r.cubic) hipLaunchKernelGGL((k_rows_rhs<T, N, true>), g, b, 0, r.stream, P, r.d, sval, rm);
-  else hipLaunchKernelGGL((k_rows_rhs<T, N, false>), g, b, 0, r.stream, P, r.d, sval, rm);
+  const int src = r.ph.gen;  // strategy-1 sources in the rows pass only for other averaged fields
+  if (r.cubic) hipLaunchKernelGGL((k_rows_rhs<T, N, true>), g, b, 0, r.stream, P, r.d, sval, rm, src);
+  else hipLaunchKernelGGL((k_rows_rhs<T, N, false>), g, b, 0, r.stream, P, r.d, sval, rm, src);
   if (r.mom) {
     const dim3 gm = row_grid<N>(2);
     if (r.cubic) hipLaunchKernelGGL((k_rows_mom<T, N, true>), gm, b, 0, r.stream, P, r.d, sval, rm);

@@ -587,18 +587,21 @@ __device__ __forceinline__ void rows_rhs_s2(const StepPtrs<T>& P, const Dims& d,
 }
 
 // Task 1, strategy 1 and the Lagrangian-mean velocity: f - u . grad g-tilde
-// (f = eta, zeta) and (t - tau) u - u . grad P; the velocity is re-read where
-// it is used.
+// and (t - tau) u - u . grad P; the velocity is re-read where it is used.  For
+// the default pair (eta, zeta), src = 0: the source f is added in the column
+// pass from the stage spectra (as the Eulerian accumulators take it), so that
+// only the advection term goes through physical space and float32 rounding;
+// other averaged fields (src = 1) take f here.
 template <typename T, int N>
 __device__ __forceinline__ void rows_rhs_s1(const StepPtrs<T>& P, const Dims& d, double s, int y, int t,
-                                            cplx<T>* buf) {
+                                            cplx<T>* buf, int src) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
   const size_t rf = d.rowfield_elems();
   const cplx<T>* ICr = P.IC + (size_t)y * d.NKXP;
   cplx<T>* RSr = P.RS + (size_t)y * d.NKXP;
   const P4<T>* Fr = P.uvhz + (size_t)y * N;
-  const T sT = T(s);
+  const T sT = T(s), fs = src ? T(1) : T(0);
   cplx<T> agt[E], apx[E], b[E];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -608,8 +611,8 @@ __device__ __forceinline__ void rows_rhs_s1(const StepPtrs<T>& P, const Dims& d,
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const P4<T> q = Fr[t + NT * e];
-      const T src = (c == 0) ? q.h : (c == 1) ? q.z : (c == 2) ? sT * q.u : sT * q.v;
-      const T r = src - (q.u * b[e].x + q.v * b[e].y);
+      const T f = (c == 0) ? fs * q.h : (c == 1) ? fs * q.z : (c == 2) ? sT * q.u : sT * q.v;
+      const T r = f - (q.u * b[e].x + q.v * b[e].y);
       if (c == 0) agt[e].x = r;
       else if (c == 1) agt[e].y = r;
       else if (c == 2) apx[e].x = r;
@@ -623,7 +626,7 @@ __device__ __forceinline__ void rows_rhs_s1(const StepPtrs<T>& P, const Dims& d,
 
 template <typename T, int N, bool CUB>
 __device__ __forceinline__ void rows_rhs_body4(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
-                                              int task, cplx<T>* lds) {
+                                              int task, cplx<T>* lds, int src) {
   using G = RowGeo<N>;
   constexpr int E = G::E, NT = G::NT;
   const int grp = row_group<NT>(), t = threadIdx.x % NT;
@@ -701,9 +704,9 @@ __device__ __forceinline__ void rows_rhs_body4(const StepPtrs<T>& P, const Dims&
     const int o = xi_task ? RS_XIX : RS_GBH;
     forward_row<T, N, true>(a, buf, t, P.tw, RSr + o * rf, RSr + (o + 1) * rf);
   } else {
-    // f - u . grad g-tilde (f = eta, zeta), or (t - tau) u - u . grad P
+    // f - u . grad g-tilde (f only when src: see rows_rhs_s1), or (t - tau) u - u . grad P
     const bool gt = (task == RT4_GT);
-    const T sT = T(s);
+    const T sT = T(s), fs = src ? T(1) : T(0);
     cplx<T> uv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -715,15 +718,15 @@ __device__ __forceinline__ void rows_rhs_body4(const StepPtrs<T>& P, const Dims&
     inverse_row<T, N>(b, buf, t, P.tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const T src = gt ? Fr[t + NT * e].h : sT * uv[e].x;
-      a[e].x = src - (uv[e].x * b[e].x + uv[e].y * b[e].y);
+      const T f = gt ? fs * Fr[t + NT * e].h : sT * uv[e].x;
+      a[e].x = f - (uv[e].x * b[e].x + uv[e].y * b[e].y);
     }
     load_pair<T, N, true, false>(b, ICr + f2 * rf, ICr + (f2 + 1) * rf, t);
     inverse_row<T, N>(b, buf, t, P.tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const T src = gt ? Fr[t + NT * e].z : sT * uv[e].y;
-      a[e].y = src - (uv[e].x * b[e].x + uv[e].y * b[e].y);
+      const T f = gt ? fs * Fr[t + NT * e].z : sT * uv[e].y;
+      a[e].y = f - (uv[e].x * b[e].x + uv[e].y * b[e].y);
     }
     const int o = gt ? RS_GTH : RS_PX;
     forward_row<T, N, true>(a, buf, t, P.tw, RSr + o * rf, RSr + (o + 1) * rf);
@@ -732,11 +735,11 @@ __device__ __forceinline__ void rows_rhs_body4(const StepPtrs<T>& P, const Dims&
 
 template <typename T, int N, bool CUB>
 __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& d, double s, int rowblock,
-                                              int task, cplx<T>* lds) {
+                                              int task, cplx<T>* lds, int src) {
   using G = RowGeo<N>;
   constexpr int NT = G::NT;
   if constexpr (!rhs_merged<T, N>()) {
-    rows_rhs_body4<T, N, CUB>(P, d, s, rowblock, task, lds);
+    rows_rhs_body4<T, N, CUB>(P, d, s, rowblock, task, lds, src);
     return;
   }
   const int grp = row_group<NT>(), t = threadIdx.x % NT;
@@ -747,7 +750,7 @@ __device__ __forceinline__ void rows_rhs_body(const StepPtrs<T>& P, const Dims& 
     if (s > 0.0) rows_rhs_s2<T, N, CUB, true>(P, d, s, y, t, buf, xs);
     else rows_rhs_s2<T, N, CUB, false>(P, d, s, y, t, buf, xs);
   } else {
-    rows_rhs_s1<T, N>(P, d, s, y, t, buf);
+    rows_rhs_s1<T, N>(P, d, s, y, t, buf, src);
   }
 }
 
@@ -762,14 +765,15 @@ __host__ __device__ constexpr int rhs_lds() {
   return (rhs_merged<T, N>() ? 2 : 1) * RowGeo<N>::RPB * RowGeo<N>::L;
 }
 
-// CUB: cubic instead of bilinear strategy-2 gathers
+// CUB: cubic instead of bilinear strategy-2 gathers; src: the strategy-1
+// sources are formed here (other averaged fields) rather than in the column pass
 template <typename T, int N, bool CUB>
 __global__ void __launch_bounds__(64 * ROW_WAVES, (rhs_waves<T, N>())) k_rows_rhs(StepPtrs<T> P, Dims d, double s,
-                                                                              int remap) {
+                                                                              int remap, int src) {
   __shared__ cplx<T> lds[rhs_lds<T, N>()];  // transform buffers (and xi, two-task form)
   int rowblock, task, z;
   xcd_split(gridDim.x, gridDim.y, rowblock, task, z, remap);  // grid = (row blocks, tasks)
-  rows_rhs_body<T, N, CUB>(P, d, s, rowblock, task, lds);
+  rows_rhs_body<T, N, CUB>(P, d, s, rowblock, task, lds, src);
 }
 
 // --------------------------------------------------------------------------
@@ -1212,14 +1216,13 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     // store, so the batch's loads are in flight together (stores to the state
     // could alias later loads as far as the compiler knows, which would
     // otherwise serialise the coefficients).
-    // The Eulerian accumulators of the default averaged fields ride along with
-    // the g-tilde and g-bar groups (E_eta with the h groups, E_zeta with the
-    // zeta groups; the g-tilde group takes the even batch positions r, the
-    // g-bar group the odd ones): they read the stage values but need no
-    // transform, and the dynamics groups already move the most data.  (Other
-    // averaged fields: groups CG_EF0/EF1.)
-    constexpr bool EULA = (G == CG_GTH || G == CG_GBH), EULB = (G == CG_GTZ || G == CG_GBZ);
-    constexpr int EPAR = (G == CG_GTH || G == CG_GTZ) ? 0 : 1;
+    // For the default averaged fields (eta, zeta) the g-tilde groups take their
+    // source f from the stage spectra, f = eta (h less H at k = 0) for g-tilde_h
+    // and f = i kx v - i ky u for g-tilde_zeta (eq. (4.1): the rows pass formed
+    // only - u . grad g-tilde), and the Eulerian accumulators ride along, since
+    // dE_f/dt = f is the same spectrum and needs no transform.  (Other averaged
+    // fields: sources in the rows pass, Eulerian means in groups CG_EF0/EF1.)
+    constexpr bool EULA = (G == CG_GTH), EULB = (G == CG_GTZ);
     const bool eul = (EULA || EULB) && !ph.gen;
     constexpr int RB0 = (DBL || DYN || EULA || EULB) ? 4 : 8;
     constexpr int RB = (E % RB0 == 0) ? RB0 : 4;
@@ -1250,7 +1253,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         }
         rk4_load<TS>(stage, Y + j, YL + j, A + j, y[q], lo[q], a[q]);
         if constexpr (EULA || EULB) {
-          if (eul && (r0i + q) % 2 == EPAR) {
+          if (eul) {
             constexpr int se = EULA ? SF_EH : SF_EZ;
             if constexpr (EULA) {
               sh[q] = Ys_in[2 * sp + j];
@@ -1270,19 +1273,18 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         const int ky = kyv[q];
         const size_t j = col + (size_t)(ky + K);
         const T kxT = T(cx.kx), kyT = T(ky);
+        cplx<T> fsrc = {T(0), T(0)};  // spectral source of the g-tilde groups
         if constexpr (EULA || EULB) {
-          // Eulerian accumulators from the stage values: dE_eta/dt = eta (h less H
-          // at k = 0), dE_zeta/dt = i kx v - i ky u
-          if (eul && r % 2 == EPAR) {
+          // dE_eta/dt = eta (h less H at k = 0), dE_zeta/dt = i kx v - i ky u
+          if (eul) {
             constexpr int se = EULA ? SF_EH : SF_EZ;
-            cplx<T> f;
             if constexpr (EULA) {
-              f = sh[q];
-              if (cx.kx == 0 && ky == 0) f.x -= HT;
+              fsrc = sh[q];
+              if (cx.kx == 0 && ky == 0) fsrc.x -= HT;
             } else {
-              f = {-kxT * sv[q].y + kyT * su[q].y, kxT * sv[q].x - kyT * su[q].x};
+              fsrc = {-kxT * sv[q].y + kyT * su[q].y, kxT * sv[q].x - kyT * su[q].x};
             }
-            rk4v<T>(stage, ey[q], el[q], ea[q], f, ph.dt);
+            rk4v<T>(stage, ey[q], el[q], ea[q], fsrc, ph.dt);
             rk4_store<T>(stage, P.Yr + se * sp + j, P.Yl + se * sp + j, P.Ar + se * sp + j, ey[q], el[q], ea[q]);
           }
         }
@@ -1309,6 +1311,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
           R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
         } else {
           R = r0[r];
+          if constexpr (EULA || EULB) R = {R.x + fsrc.x, R.y + fsrc.y};
           (void)hv;
         }
         const cplx<TS> Rk = {TS(R.x), TS(R.y)};
@@ -1408,7 +1411,7 @@ __global__ void __launch_bounds__(64 * ROW_WAVES, (rhs_waves<T, N>())) k_rows_rh
   // time since the interval start, from integers (as the single-run path)
   const double c = (stage == 0) ? 0.0 : ((stage == 3) ? 1.0 : 0.5);
   const double s = (double(*R.counter) + c) * R.ph.dt;
-  rows_rhs_body<T, N, CUB>(R.P, Dims::make(N), s, rowblock, task, lds);
+  rows_rhs_body<T, N, CUB>(R.P, Dims::make(N), s, rowblock, task, lds, R.ph.gen);
 }
 
 template <typename T, int N, bool CUB>
