@@ -479,33 +479,12 @@ __global__ void __launch_bounds__((DynGeo<T, N>::THREADS), (dyn_waves<T>())) k_r
 // Tasks, one wavefront per row and task.  Float runs of N >= 512 take two:
 //   RT_S2  strategy 2: both xi components (eq. (4.5a)) and g-bar of eta and
 //          zeta (eq. (4.5b)), from one transform of xi and one gather
-//   RT_S1  strategy 1: g-tilde of eta and zeta (eq. (4.1)) and both P
-//          components (eq. (3.9) in P form)
+//   RT_S1  strategy 1: g-tilde of eta and zeta (eq. (4.1); their sources are
+//          added in the column pass) and both P components (eq. (3.9) in P form)
 // (each wave holds two output pairs; the rows' 2N waves at two per SIMD run in
 // one round).  Smaller grids and float64, where more, shorter waves pay
 // better, take four: RT4_XI (xi), RT4_GB (g-bar), RT4_GT (g-tilde), RT4_P (P),
 // the two strategy-2 tasks each transforming xi and gathering at x + xi.
-// gathers of (u, v) (PAIR 0) or (eta, zeta) (PAIR 1) at x + xi for the E points
-// of a lane, in place of the displacements held in a
-template <typename T, int N, bool CUB, int PAIR>
-__device__ __forceinline__ void gather_row(cplx<T> (&a)[fft_E<N>()], const P4<T>* __restrict__ F, int t, int y) {
-  constexpr int E = fft_E<N>(), NT = N / E;
-  if constexpr (CUB) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      a[e] = gather2_cubic<T, N, PAIR>(F, t + NT * e, y, a[e].x, a[e].y);
-      sched_fence();
-    }
-  } else {
-    constexpr int GG = 4;
-#pragma unroll
-    for (int e0 = 0; e0 < E; e0 += GG) {
-#pragma unroll
-      for (int e = e0; e < e0 + GG; ++e) a[e] = gather2<T, N, PAIR>(F, t + NT * e, y, a[e].x, a[e].y);
-      sched_fence();
-    }
-  }
-}
 
 // The mean right-hand-side rows pass, two tasks per row.
 // Task 0, strategy 2: with w = xi / (t - tau) the partial-mean velocity (u / 2
