@@ -1198,10 +1198,14 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
     // For the default averaged fields (eta, zeta) the g-tilde groups take their
     // source f from the stage spectra, f = eta (h less H at k = 0) for g-tilde_h
     // and f = i kx v - i ky u for g-tilde_zeta (eq. (4.1): the rows pass formed
-    // only - u . grad g-tilde), and the Eulerian accumulators ride along, since
-    // dE_f/dt = f is the same spectrum and needs no transform.  (Other averaged
-    // fields: sources in the rows pass, Eulerian means in groups CG_EF0/EF1.)
-    constexpr bool EULA = (G == CG_GTH), EULB = (G == CG_GTZ);
+    // only - u . grad g-tilde).  The Eulerian accumulators, dE_f/dt = f, the same
+    // spectrum with no transform, ride along with the g-tilde groups (even batch
+    // positions r, where f is at hand) and the g-bar groups (odd ones), which
+    // balances the blocks.  (Other averaged fields: sources in the rows pass,
+    // Eulerian means in groups CG_EF0/EF1.)
+    constexpr bool EULA = (G == CG_GTH || G == CG_GBH), EULB = (G == CG_GTZ || G == CG_GBZ);
+    constexpr bool SRCG = (G == CG_GTH || G == CG_GTZ);
+    constexpr int EPAR = SRCG ? 0 : 1;
     const bool eul = (EULA || EULB) && !ph.gen;
     constexpr int RB0 = (DBL || DYN || EULA || EULB) ? 4 : 8;
     constexpr int RB = (E % RB0 == 0) ? RB0 : 4;
@@ -1232,14 +1236,17 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         }
         rk4_load<TS>(stage, Y + j, YL + j, A + j, y[q], lo[q], a[q]);
         if constexpr (EULA || EULB) {
-          if (eul) {
-            constexpr int se = EULA ? SF_EH : SF_EZ;
+          const bool acc = (r0i + q) % 2 == EPAR;
+          if (eul && (SRCG || acc)) {
             if constexpr (EULA) {
               sh[q] = Ys_in[2 * sp + j];
             } else {
               su[q] = Ys_in[0 * sp + j];
               sv[q] = Ys_in[1 * sp + j];
             }
+          }
+          if (eul && acc) {
+            constexpr int se = EULA ? SF_EH : SF_EZ;
             rk4_load<T>(stage, P.Yr + se * sp + j, P.Yl + se * sp + j, P.Ar + se * sp + j, ey[q], el[q], ea[q]);
           }
         }
@@ -1252,17 +1259,20 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
         const int ky = kyv[q];
         const size_t j = col + (size_t)(ky + K);
         const T kxT = T(cx.kx), kyT = T(ky);
-        cplx<T> fsrc = {T(0), T(0)};  // spectral source of the g-tilde groups
+        cplx<T> fsrc = {T(0), T(0)};  // f = eta or zeta from the stage spectra
         if constexpr (EULA || EULB) {
           // dE_eta/dt = eta (h less H at k = 0), dE_zeta/dt = i kx v - i ky u
-          if (eul) {
-            constexpr int se = EULA ? SF_EH : SF_EZ;
+          const bool acc = r % 2 == EPAR;
+          if (eul && (SRCG || acc)) {
             if constexpr (EULA) {
               fsrc = sh[q];
               if (cx.kx == 0 && ky == 0) fsrc.x -= HT;
             } else {
               fsrc = {-kxT * sv[q].y + kyT * su[q].y, kxT * sv[q].x - kyT * su[q].x};
             }
+          }
+          if (eul && acc) {
+            constexpr int se = EULA ? SF_EH : SF_EZ;
             rk4v<T>(stage, ey[q], el[q], ea[q], fsrc, ph.dt);
             rk4_store<T>(stage, P.Yr + se * sp + j, P.Yl + se * sp + j, P.Ar + se * sp + j, ey[q], el[q], ea[q]);
           }
@@ -1290,7 +1300,7 @@ __device__ __forceinline__ void column_group(const ColCtx<T, N, C>& cx, const St
           R = {kxT * fx.y + kyT * fy.y - hv * h.x, -kxT * fx.x - kyT * fy.x - hv * h.y};
         } else {
           R = r0[r];
-          if constexpr (EULA || EULB) R = {R.x + fsrc.x, R.y + fsrc.y};
+          if constexpr (SRCG) R = {R.x + fsrc.x, R.y + fsrc.y};
           (void)hv;
         }
         const cplx<TS> Rk = {TS(R.x), TS(R.y)};
