@@ -94,9 +94,9 @@ void launch_rows_rhs(RunView& r, const StepPtrs<T>& P, double sval) {
 // Two-stream form of the steps.  Per stage the dependencies are
 //   rows_dyn(i)  <- the dynamics column groups of stage i-1 (their outputs),
 //                   rows_rhs(i-1) (it reads the physical fields rows_dyn rewrites)
-//                   and the mean column groups of stage i-1 (the Eulerian
-//                   accumulators among them read the stage values that the
-//                   dynamics groups of stage i overwrite),
+//                   and the mean column groups of stage i-1 (the strategy-1
+//                   sources and Eulerian accumulators among them read the stage
+//                   values that the dynamics groups of stage i overwrite),
 //   rows_rhs(i)  <- rows_dyn(i) and the mean column groups of stage i-1,
 //   dynamics column groups(i) <- rows_dyn(i),  mean column groups(i) <- rows_rhs(i),
 // and no pass writes what a pass it may overlap with reads.  The auxiliary
